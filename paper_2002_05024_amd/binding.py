@@ -1,0 +1,286 @@
+"""ctypes binding of ``libneig.so`` (the C ABI in ``include/neig.h``).
+
+Argument marshalling only: every numerical step runs in the library's HIP
+kernels.  Matrices are torch float64 CUDA (HIP) tensors in column-major layout
+(``stride(0) == 1``, leading dimension ``stride(1)``); the calls run on
+``torch.cuda.current_stream()`` unless a stream is given.  There is no CPU
+fallback: if the library is missing or the tensors are not on the GPU, the
+call raises :class:`NeigError`.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from collections import namedtuple
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB_PATH = os.path.join(_HERE, "libneig.so")
+_lib = None
+
+_i = ctypes.c_int
+_vp = ctypes.c_void_p
+_ip = ctypes.POINTER(ctypes.c_int)
+_dp = ctypes.POINTER(ctypes.c_double)
+
+
+class NeigError(RuntimeError):
+    pass
+
+
+class Params(ctypes.Structure):
+    _fields_ = [
+        ("ns", _i),
+        ("nw", _i),
+        ("nmin", _i),
+        ("chain", _i),
+        ("chase_w", _i),
+        ("deflation", _i),
+        ("maxit", _i),
+        ("nibble", _i),
+        ("exc", _i),
+        ("reserved", _i * 7),
+    ]
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [
+        ("sweeps", ctypes.c_longlong),
+        ("aeds", ctypes.c_longlong),
+        ("aed_deflated", ctypes.c_longlong),
+        ("shifts_used", ctypes.c_longlong),
+        ("exceptional", ctypes.c_longlong),
+        ("small_solves", ctypes.c_longlong),
+        ("swap_failures", ctypes.c_longlong),
+        ("iterations", ctypes.c_longlong),
+        ("gemm_flops", ctypes.c_double),
+        ("chase_flops", ctypes.c_double),
+        ("small_flops", ctypes.c_double),
+        ("t_total_ms", ctypes.c_double),
+        ("t_aed_ms", ctypes.c_double),
+        ("t_sweep_ms", ctypes.c_double),
+        ("t_small_ms", ctypes.c_double),
+        ("reserved", ctypes.c_double * 8),
+    ]
+
+
+SchurResult = namedtuple("SchurResult", "wr wi Z info")
+
+
+def library_path() -> str:
+    return _LIB_PATH
+
+
+def load_library():
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(_LIB_PATH):
+        raise NeigError(f"{_LIB_PATH} is not built (run __graft_entry__.build())")
+    lib = ctypes.CDLL(_LIB_PATH)
+    lib.neig_schur.argtypes = [_i, _vp, _i, _vp, _i, _vp, _vp, _vp]
+    lib.neig_schur.restype = _i
+    lib.neig_schur_batched.argtypes = [_i, _ip, _vp, _ip, _vp, _ip, _vp, _vp, _vp, _vp]
+    lib.neig_schur_batched.restype = _i
+    lib.neig_sweep.argtypes = [_i, _vp, _i, _vp, _i, _i, _i, _i, _dp, _dp, _vp]
+    lib.neig_sweep.restype = _i
+    lib.neig_aed.argtypes = [_i, _vp, _i, _vp, _i, _i, _i, _i, _ip, _ip, _dp, _dp, _vp]
+    lib.neig_aed.restype = _i
+    lib.neig_small_schur.argtypes = [_i, _vp, _i, _vp, _i, _vp, _vp, _vp]
+    lib.neig_small_schur.restype = _i
+    lib.neig_set_params.argtypes = [ctypes.POINTER(Params)]
+    lib.neig_set_params.restype = _i
+    lib.neig_get_params.argtypes = [ctypes.POINTER(Params)]
+    lib.neig_get_params.restype = _i
+    lib.neig_get_stats.argtypes = [ctypes.POINTER(Stats)]
+    lib.neig_get_stats.restype = _i
+    lib.neig_finalize.argtypes = []
+    lib.neig_finalize.restype = None
+    lib.neig_version.argtypes = []
+    lib.neig_version.restype = ctypes.c_char_p
+    _lib = lib
+    return lib
+
+
+def _torch():
+    import torch
+
+    return torch
+
+
+def _check_matrix(name, t, n):
+    torch = _torch()
+    if not isinstance(t, torch.Tensor):
+        raise NeigError(f"{name} must be a torch tensor")
+    if t.dtype != torch.float64:
+        raise NeigError(f"{name} must be float64")
+    if not t.is_cuda:
+        raise NeigError(f"{name} must be a GPU tensor (no CPU path)")
+    if t.dim() != 2 or t.shape[0] != n or t.shape[1] != n:
+        raise NeigError(f"{name} must be {n}x{n}")
+    if n > 0 and (t.stride(0) != 1 or t.stride(1) < n):
+        raise NeigError(f"{name} must be column-major (stride(0) == 1, stride(1) >= n)")
+    return max(1, t.stride(1)) if n > 0 else 1
+
+
+def _stream_ptr(stream):
+    torch = _torch()
+    s = torch.cuda.current_stream() if stream is None else stream
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def colmajor(a, device="cuda"):
+    """A column-major float64 device copy of a numpy array or tensor."""
+    torch = _torch()
+    import numpy as np
+
+    if isinstance(a, torch.Tensor):
+        a = a.detach().cpu().numpy()
+    a = np.asarray(a, dtype=np.float64)
+    return torch.from_numpy(np.ascontiguousarray(a.T)).to(device).t()
+
+
+def _raise(name, info):
+    if info < 0:
+        if info <= -100:
+            raise NeigError(f"{name}: HIP runtime error {-100 - info}")
+        raise NeigError(f"{name}: argument {-info} is invalid")
+
+
+def schur(H, Z=None, stream=None) -> SchurResult:
+    """Real Schur form in place: on return H holds S and Z holds Z_in Q, with
+    H_in = Z_out S Z_out^T when Z_in = I (eq. 4).  Z=None starts from I.
+    info > 0 counts unconverged eigenvalues (the call can be repeated)."""
+    torch = _torch()
+    lib = load_library()
+    n = H.shape[0]
+    ldh = _check_matrix("H", H, n)
+    if Z is None:
+        Z = torch.eye(n, dtype=torch.float64, device=H.device).t().contiguous().t()
+    ldz = _check_matrix("Z", Z, n)
+    wr = torch.empty(n, dtype=torch.float64, device=H.device)
+    wi = torch.empty(n, dtype=torch.float64, device=H.device)
+    info = lib.neig_schur(n, ctypes.c_void_p(H.data_ptr()), ldh, ctypes.c_void_p(Z.data_ptr()), ldz,
+                          ctypes.c_void_p(wr.data_ptr()), ctypes.c_void_p(wi.data_ptr()), _stream_ptr(stream))
+    _raise("neig_schur", info)
+    return SchurResult(wr, wi, Z, info)
+
+
+def small_schur(H, Z=None, stream=None) -> SchurResult:
+    """Real Schur form of a matrix small enough for one workgroup's LDS (the
+    double-shift QR used for small blocks and for AED windows), in place."""
+    torch = _torch()
+    lib = load_library()
+    n = H.shape[0]
+    ldh = _check_matrix("H", H, n)
+    if Z is None:
+        Z = torch.eye(n, dtype=torch.float64, device=H.device).t().contiguous().t()
+    ldz = _check_matrix("Z", Z, n)
+    wr = torch.empty(n, dtype=torch.float64, device=H.device)
+    wi = torch.empty(n, dtype=torch.float64, device=H.device)
+    info = lib.neig_small_schur(n, ctypes.c_void_p(H.data_ptr()), ldh, ctypes.c_void_p(Z.data_ptr()), ldz,
+                                ctypes.c_void_p(wr.data_ptr()), ctypes.c_void_p(wi.data_ptr()),
+                                _stream_ptr(stream))
+    _raise("neig_small_schur", info)
+    return SchurResult(wr, wi, Z, info)
+
+
+def sweep(H, Z, ktop, kbot, shifts_re, shifts_im, stream=None) -> int:
+    """One multishift QR sweep over the active block [ktop, kbot] with the given
+    shifts (complex pairs adjacent), H and Z updated in place."""
+    import numpy as np
+
+    lib = load_library()
+    n = H.shape[0]
+    ldh = _check_matrix("H", H, n)
+    ldz = _check_matrix("Z", Z, n)
+    sr = np.ascontiguousarray(shifts_re, dtype=np.float64)
+    si = np.ascontiguousarray(shifts_im, dtype=np.float64)
+    ns = int(sr.size)
+    info = lib.neig_sweep(n, ctypes.c_void_p(H.data_ptr()), ldh, ctypes.c_void_p(Z.data_ptr()), ldz,
+                          int(ktop), int(kbot), ns, sr.ctypes.data_as(_dp), si.ctypes.data_as(_dp),
+                          _stream_ptr(stream))
+    _raise("neig_sweep", info)
+    return info
+
+
+def aed(H, Z, ktop, kbot, nw, stream=None):
+    """One aggressive-early-deflation step on the trailing window of [ktop, kbot].
+    Returns (nd, shifts_re, shifts_im): deflated count and the undeflated Ritz
+    values (shift candidates, bottom-most last)."""
+    import numpy as np
+
+    lib = load_library()
+    n = H.shape[0]
+    ldh = _check_matrix("H", H, n)
+    ldz = _check_matrix("Z", Z, n)
+    nd = ctypes.c_int(0)
+    nsh = ctypes.c_int(0)
+    sr = np.zeros(max(nw, 1))
+    si = np.zeros(max(nw, 1))
+    info = lib.neig_aed(n, ctypes.c_void_p(H.data_ptr()), ldh, ctypes.c_void_p(Z.data_ptr()), ldz,
+                        int(ktop), int(kbot), int(nw), ctypes.byref(nd), ctypes.byref(nsh),
+                        sr.ctypes.data_as(_dp), si.ctypes.data_as(_dp), _stream_ptr(stream))
+    _raise("neig_aed", info)
+    k = nsh.value
+    return nd.value, sr[:k].copy(), si[:k].copy()
+
+
+def schur_batched(Hs, Zs=None, stream=None):
+    """Real Schur forms of a list of independent problems of uneven size in one
+    asynchronous call.  Returns (wr list, wi list, Z list, info tensor)."""
+    torch = _torch()
+    import numpy as np
+
+    lib = load_library()
+    b = len(Hs)
+    dev = Hs[0].device if b else torch.device("cuda")
+    if Zs is None:
+        Zs = [torch.eye(h.shape[0], dtype=torch.float64, device=dev).t().contiguous().t() for h in Hs]
+    ns = np.array([h.shape[0] for h in Hs], dtype=np.int32)
+    ldh = np.array([_check_matrix("H", h, int(k)) for h, k in zip(Hs, ns)], dtype=np.int32)
+    ldz = np.array([_check_matrix("Z", z, int(k)) for z, k in zip(Zs, ns)], dtype=np.int32)
+    wrs = [torch.empty(int(k), dtype=torch.float64, device=dev) for k in ns]
+    wis = [torch.empty(int(k), dtype=torch.float64, device=dev) for k in ns]
+    ptrs = torch.tensor([h.data_ptr() for h in Hs] + [z.data_ptr() for z in Zs]
+                        + [w.data_ptr() for w in wrs] + [w.data_ptr() for w in wis],
+                        dtype=torch.int64, device=dev)
+    info = torch.zeros(b, dtype=torch.int32, device=dev)
+    base = ptrs.data_ptr()
+    rc = lib.neig_schur_batched(b, ns.ctypes.data_as(_ip), ctypes.c_void_p(base), ldh.ctypes.data_as(_ip),
+                                ctypes.c_void_p(base + 8 * b), ldz.ctypes.data_as(_ip),
+                                ctypes.c_void_p(base + 16 * b), ctypes.c_void_p(base + 24 * b),
+                                ctypes.c_void_p(info.data_ptr()), _stream_ptr(stream))
+    _raise("neig_schur_batched", rc)
+    return wrs, wis, Zs, info, ptrs
+
+
+def set_params(**kw) -> None:
+    lib = load_library()
+    p = Params()
+    lib.neig_get_params(ctypes.byref(p))
+    for k, v in kw.items():
+        if not hasattr(p, k) or k == "reserved":
+            raise NeigError(f"unknown parameter {k}")
+        setattr(p, k, int(v))
+    rc = lib.neig_set_params(ctypes.byref(p))
+    if rc != 0:
+        raise NeigError(f"neig_set_params: invalid field {-rc}")
+
+
+def get_params() -> dict:
+    lib = load_library()
+    p = Params()
+    lib.neig_get_params(ctypes.byref(p))
+    return {f: getattr(p, f) for f, _ in Params._fields_ if f != "reserved"}
+
+
+def get_stats() -> dict:
+    lib = load_library()
+    s = Stats()
+    lib.neig_get_stats(ctypes.byref(s))
+    return {f: getattr(s, f) for f, _ in Stats._fields_ if f != "reserved"}
+
+
+def finalize() -> None:
+    if _lib is not None:
+        _lib.neig_finalize()
