@@ -38,7 +38,8 @@ class Params(ctypes.Structure):
         ("maxit", _i),
         ("nibble", _i),
         ("exc", _i),
-        ("reserved", _i * 7),
+        ("timing", _i),
+        ("reserved", _i * 6),
     ]
 
 
@@ -59,7 +60,19 @@ class Stats(ctypes.Structure):
         ("t_aed_ms", ctypes.c_double),
         ("t_sweep_ms", ctypes.c_double),
         ("t_small_ms", ctypes.c_double),
-        ("reserved", ctypes.c_double * 8),
+        ("alg_flops", ctypes.c_double),
+        ("gpu_update_ms", ctypes.c_double),
+        ("gpu_chase_ms", ctypes.c_double),
+        ("gpu_aed_ms", ctypes.c_double),
+        ("gpu_small_ms", ctypes.c_double),
+        ("gpu_other_ms", ctypes.c_double),
+        ("n_update", ctypes.c_double),
+        ("n_chase", ctypes.c_double),
+        ("aed_qr_iters", ctypes.c_double),
+        ("aed_swaps", ctypes.c_double),
+        ("aed_cyc_qr", ctypes.c_double),
+        ("aed_cyc_defl", ctypes.c_double),
+        ("aed_cyc_hess", ctypes.c_double),
     ]
 
 

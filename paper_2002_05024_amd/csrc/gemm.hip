@@ -1,0 +1,125 @@
+// gemm.hip -- the left / right update tasks (Section 3.2): apply a window's
+// accumulated orthogonal factor U (w x w, w <= 128, given as U^T) to an
+// off-diagonal strip of H or Z, in place, with FP64 matrix-core instructions
+// (v_mfma_f64_16x16x4_f64).
+//
+//   side 0 (left):  C (w x len)  <- U^T C   the rows of a window, right of it
+//   side 1 (right): C (len x w)  <- C U     the columns of a window, above it / Z
+//
+// One launch carries several strips ("tasks"); each workgroup owns a 64-wide
+// slice of one strip (64 columns for side 0, 64 rows for side 1), reads all of
+// it before writing, so in-place is safe.  Four waves; each wave owns one
+// 16-wide column (side 0) or row (side 1) tile of the slice and loops over all
+// of the window's 16-row tiles, so the U^T operand streams from L2 while the
+// strip operand comes from LDS (side 0) or straight from HBM (side 1).
+//
+// Operand layouts of v_mfma_f64_16x16x4_f64 (lane l, 64 lanes): A(16x4) element
+// (l%16, l/16); B(4x16) element (l/16, l%16); the four accumulator doubles of
+// lane l hold D(l/16 + 4r, l%16), r = 0..3.
+#include "neig_dev.h"
+
+#define UPD_THREADS 256
+#define UPD_MAX_TASKS 48
+#define UPD_WMAX 128
+#define UPD_SLICE 64
+
+struct UpdTask {
+    double *C;
+    const double *Ut;
+    int ldc, ldu, w, len, side, tile0;
+};
+
+struct UpdArgs {
+    UpdTask t[UPD_MAX_TASKS];
+    int ntask;
+};
+
+__device__ __forceinline__ neig_d4 mfma16(double a, double b, neig_d4 c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+
+extern "C" __global__ void __launch_bounds__(UPD_THREADS)
+k_update(UpdArgs args) {
+    extern __shared__ double Cs[];
+    int ti = 0;
+    const int bid = blockIdx.x;
+    while (ti + 1 < args.ntask && args.t[ti + 1].tile0 <= bid) ++ti;
+    const UpdTask T = args.t[ti];
+    const int tile = bid - T.tile0;
+    const int lane = threadIdx.x & 63;
+    const int q = threadIdx.x >> 6;
+    const int w = T.w;
+    const int wp = (w + 15) & ~15;
+    const int kp = (w + 3) & ~3;
+    const int nrt = wp >> 4;
+    const int li = lane & 15, lk = lane >> 4;
+    neig_d4 acc[8];
+#pragma unroll
+    for (int r = 0; r < 8; ++r) acc[r] = (neig_d4){0.0, 0.0, 0.0, 0.0};
+
+    if (T.side == 0) {
+        const int c0 = tile * UPD_SLICE;
+        const int ldcs = wp + 1;
+        for (int idx = threadIdx.x; idx < wp * UPD_SLICE; idx += UPD_THREADS) {
+            const int r = idx % wp, c = idx / wp;
+            double v = 0.0;
+            if (r < w && c0 + c < T.len) v = AT(T.C, T.ldc, r, c0 + c);
+            Cs[r + c * ldcs] = v;
+        }
+        __syncthreads();
+        const int cb = 16 * q + li;
+        for (int k = 0; k < kp; k += 4) {
+            const int kk = k + lk;
+            const double b = Cs[kk + cb * ldcs];
+#pragma unroll
+            for (int rt = 0; rt < 8; ++rt) {
+                if (rt < nrt) {
+                    const int ar = 16 * rt + li;
+                    const double a = (ar < w && kk < w) ? AT(T.Ut, T.ldu, ar, kk) : 0.0;
+                    acc[rt] = mfma16(a, b, acc[rt]);
+                }
+            }
+        }
+        const int col = c0 + 16 * q + li;
+        if (col < T.len) {
+#pragma unroll
+            for (int rt = 0; rt < 8; ++rt) {
+                if (rt < nrt) {
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) {
+                        const int row = 16 * rt + lk + 4 * r;
+                        if (row < w) AT(T.C, T.ldc, row, col) = acc[rt][r];
+                    }
+                }
+            }
+        }
+    } else {
+        const int rbase = tile * UPD_SLICE + 16 * q;
+        const int arow = rbase + li;
+        for (int k = 0; k < kp; k += 4) {
+            const int kk = k + lk;
+            const double a = (arow < T.len && kk < w) ? AT(T.C, T.ldc, arow, kk) : 0.0;
+#pragma unroll
+            for (int ct = 0; ct < 8; ++ct) {
+                if (ct < nrt) {
+                    const int bc = 16 * ct + li;
+                    const double b = (bc < w && kk < w) ? AT(T.Ut, T.ldu, bc, kk) : 0.0;
+                    acc[ct] = mfma16(a, b, acc[ct]);
+                }
+            }
+        }
+#pragma unroll
+        for (int ct = 0; ct < 8; ++ct) {
+            if (ct < nrt) {
+                const int col = 16 * ct + li;
+                if (col < w) {
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) {
+                        const int row = rbase + lk + 4 * r;
+                        if (row < T.len) AT(T.C, T.ldc, row, col) = acc[ct][r];
+                    }
+                }
+            }
+        }
+    }
+}

@@ -1,0 +1,714 @@
+// small.hip -- one-workgroup kernels that keep a whole small matrix in LDS.
+//
+//  * k_small_qr: the double-shift QR iteration (the two-shift case of the bulge
+//    chase in Section 3.2) on an m x m diagonal block, m <= NEIG_SMALL_MAX, with
+//    its orthogonal factor accumulated in LDS.  Used for the final small active
+//    blocks and for whole problems that fit.
+//  * k_aed: aggressive early deflation (Section 3.2, "AED step") on a trailing
+//    window that fits in LDS: window Schur form by the same QR, spike test of
+//    every diagonal block from the bottom up, failing blocks moved to the top of
+//    the window by swaps of adjacent diagonal blocks (Section 3.2, the
+//    Bai-Demmel block swap), then a Householder Hessenberg reduction of the
+//    remaining spike and undeflated part.
+//
+// Both run as ONE wavefront (64 lanes): every LDS access of a step is issued by
+// the same wave, so the steps need no cross-wave barriers, and scalar decisions
+// are computed redundantly by all lanes from the same LDS values.
+#include "neig_dev.h"
+#include <climits>
+
+#define LANES 64
+
+// rows r, r+1 of M, columns c0..c1: (x, y) <- (cs x + sn y, -sn x + cs y)
+__device__ __forceinline__ void lds_rot_rows(double *M, int ld, int r, int c0, int c1, double cs, double sn) {
+    for (int j = c0 + (int)threadIdx.x; j <= c1; j += LANES) {
+        double x = AT(M, ld, r, j), y = AT(M, ld, r + 1, j);
+        AT(M, ld, r, j) = cs * x + sn * y;
+        AT(M, ld, r + 1, j) = -sn * x + cs * y;
+    }
+}
+
+// columns c, c+1 of M, rows r0..r1
+__device__ __forceinline__ void lds_rot_cols(double *M, int ld, int c, int r0, int r1, double cs, double sn) {
+    for (int i = r0 + (int)threadIdx.x; i <= r1; i += LANES) {
+        double x = AT(M, ld, i, c), y = AT(M, ld, i, c + 1);
+        AT(M, ld, i, c) = cs * x + sn * y;
+        AT(M, ld, i, c + 1) = -sn * x + cs * y;
+    }
+}
+
+// Standardise the 2x2 block at (j, j) of the m x m matrix T (rotation applied to
+// whole rows and columns of T and to the columns of Q).
+__device__ void lds_standardise(double *T, int ldt, double *Q, int ldq, int m, int j) {
+    Std2 o = std2x2(AT(T, ldt, j, j), AT(T, ldt, j, j + 1), AT(T, ldt, j + 1, j), AT(T, ldt, j + 1, j + 1));
+    __syncthreads();
+    if (!(o.cs == 1.0 && o.sn == 0.0)) {
+        lds_rot_rows(T, ldt, j, j + 2, m - 1, o.cs, o.sn);
+        lds_rot_cols(T, ldt, j, 0, j - 1, o.cs, o.sn);
+        lds_rot_cols(Q, ldq, j, 0, m - 1, o.cs, o.sn);
+    }
+    if (threadIdx.x == 0) {
+        AT(T, ldt, j, j) = o.a; AT(T, ldt, j, j + 1) = o.b;
+        AT(T, ldt, j + 1, j) = o.c; AT(T, ldt, j + 1, j + 1) = o.d;
+    }
+    __syncthreads();
+}
+
+// One implicit double-shift step on the active rows l..i of the LDS matrix
+// (updates span the whole m x m matrix and Q's columns).
+__device__ void lds_francis(double *T, int ldt, double *Q, int ldq, int m, int l, int i, double tr, double det) {
+    const int lane = threadIdx.x;
+    for (int k = l; k <= i - 1; ++k) {
+        const int m3 = (k <= i - 2) ? 3 : 2;
+        double x0, x1, x2;
+        if (k == l) {
+            double h00 = AT(T, ldt, l, l), h01 = AT(T, ldt, l, l + 1);
+            double h10 = AT(T, ldt, l + 1, l), h11 = AT(T, ldt, l + 1, l + 1);
+            double h21 = AT(T, ldt, l + 2, l + 1);
+            double sc = fmax(fmax(fabs(h00), fabs(h01)), fmax(fmax(fabs(h10), fabs(h11)), fabs(h21)));
+            sc = fmax(sc, fmax(fabs(tr), sqrt(fabs(det))));
+            if (sc == 0.0) sc = 1.0;
+            double a = h00 / sc, b = h01 / sc, c = h10 / sc, d = h11 / sc, e = h21 / sc;
+            double t = tr / sc, dt = det / (sc * sc);
+            x0 = a * a + b * c - t * a + dt;
+            x1 = c * (a + d - t);
+            x2 = c * e;
+        } else {
+            x0 = AT(T, ldt, k, k - 1);
+            x1 = AT(T, ldt, k + 1, k - 1);
+            x2 = (m3 == 3) ? AT(T, ldt, k + 2, k - 1) : 0.0;
+        }
+        Refl r = make_refl(x0, x1, x2);
+        __syncthreads();
+        if (r.tau == 0.0) continue;
+        if (k > l && lane == 0) {
+            AT(T, ldt, k, k - 1) = r.beta;
+            AT(T, ldt, k + 1, k - 1) = 0.0;
+            if (m3 == 3) AT(T, ldt, k + 2, k - 1) = 0.0;
+        }
+        for (int j = k + lane; j < m; j += LANES) {
+            double a = AT(T, ldt, k, j), b = AT(T, ldt, k + 1, j);
+            double c = (m3 == 3) ? AT(T, ldt, k + 2, j) : 0.0;
+            double t = r.tau * (a + r.v1 * b + r.v2 * c);
+            AT(T, ldt, k, j) = a - t;
+            AT(T, ldt, k + 1, j) = b - t * r.v1;
+            if (m3 == 3) AT(T, ldt, k + 2, j) = c - t * r.v2;
+        }
+        __syncthreads();
+        const int rmax = (k + 3 < i) ? k + 3 : i;
+        for (int rr = lane; rr <= rmax; rr += LANES) {
+            double a = AT(T, ldt, rr, k), b = AT(T, ldt, rr, k + 1);
+            double c = (m3 == 3) ? AT(T, ldt, rr, k + 2) : 0.0;
+            double t = r.tau * (a + r.v1 * b + r.v2 * c);
+            AT(T, ldt, rr, k) = a - t;
+            AT(T, ldt, rr, k + 1) = b - t * r.v1;
+            if (m3 == 3) AT(T, ldt, rr, k + 2) = c - t * r.v2;
+        }
+        for (int rr = lane; rr < m; rr += LANES) {
+            double a = AT(Q, ldq, rr, k), b = AT(Q, ldq, rr, k + 1);
+            double c = (m3 == 3) ? AT(Q, ldq, rr, k + 2) : 0.0;
+            double t = r.tau * (a + r.v1 * b + r.v2 * c);
+            AT(Q, ldq, rr, k) = a - t;
+            AT(Q, ldq, rr, k + 1) = b - t * r.v1;
+            if (m3 == 3) AT(Q, ldq, rr, k + 2) = c - t * r.v2;
+        }
+        __syncthreads();
+    }
+}
+
+// Double-shift QR iteration on the m x m LDS matrix T (upper Hessenberg) with Q
+// accumulated.  Returns 0, or i+1 when rows/cols 0..i did not converge within
+// maxit iterations.  *iters receives the iteration count.
+__device__ int lds_small_qr(double *T, int ldt, double *Q, int ldq, int m, double hnorm, double smlnum, int maxit,
+                            int *iters) {
+    const int lane = threadIdx.x;
+    int i = m - 1, its = 0, total = 0;
+    while (i >= 0) {
+        int l = 0;
+        for (int base = i; base >= 1; base -= LANES) {
+            int k = base - lane;
+            bool neg = false;
+            if (k >= 1) neg = negligible_sub(AT(T, ldt, k, k - 1), AT(T, ldt, k - 1, k - 1), AT(T, ldt, k, k), hnorm, smlnum);
+            unsigned long long mask = __ballot(neg);
+            if (mask) {
+                l = base - (__ffsll(mask) - 1);
+                break;
+            }
+        }
+        __syncthreads();
+        if (l > 0 && lane == 0) AT(T, ldt, l, l - 1) = 0.0;
+        __syncthreads();
+        if (l == i) {
+            --i;
+            its = 0;
+            continue;
+        }
+        if (l == i - 1) {
+            lds_standardise(T, ldt, Q, ldq, m, i - 1);
+            i -= 2;
+            its = 0;
+            continue;
+        }
+        if (total >= maxit) {
+            *iters = total;
+            return i + 1;
+        }
+        ++total;
+        ++its;
+        double tr, det;
+        if (its == 10 || its == 20) {
+            double s = fabs(AT(T, ldt, i, i - 1)) + fabs(AT(T, ldt, i - 1, i - 2));
+            double x = AT(T, ldt, i, i);
+            tr = 2.0 * x + 1.5 * s;
+            det = x * x + 1.5 * s * x + s * s;
+        } else {
+            double a = AT(T, ldt, i - 1, i - 1), b = AT(T, ldt, i - 1, i);
+            double c = AT(T, ldt, i, i - 1), d = AT(T, ldt, i, i);
+            tr = a + d;
+            det = a * d - b * c;
+        }
+        lds_francis(T, ldt, Q, ldq, m, l, i, tr, det);
+    }
+    *iters = total;
+    return 0;
+}
+
+// Load the m x m diagonal block of H at (off, off) into T (zeros below the
+// subdiagonal) and set Q = I.
+__device__ void lds_load_block(const double *H, int ldh, int off, int m, double *T, int ldt, double *Q, int ldq) {
+    for (int j = 0; j < m; ++j) {
+        for (int i = threadIdx.x; i < m; i += LANES) {
+            AT(T, ldt, i, j) = (i <= j + 1) ? AT(H, ldh, off + i, off + j) : 0.0;
+            AT(Q, ldq, i, j) = (i == j) ? 1.0 : 0.0;
+        }
+    }
+    __syncthreads();
+}
+
+// Write T back to H's diagonal block and Q^T to Ut (column-major, ld ldut).
+__device__ void lds_store(double *H, int ldh, int off, int m, const double *T, int ldt, const double *Q, int ldq,
+                          double *Ut, int ldut) {
+    for (int j = 0; j < m; ++j) {
+        for (int i = threadIdx.x; i < m; i += LANES) {
+            AT(H, ldh, off + i, off + j) = (i <= j + 1) ? AT(T, ldt, i, j) : 0.0;
+            AT(Ut, ldut, i, j) = AT(Q, ldq, j, i);
+        }
+    }
+}
+
+extern "C" __global__ void __launch_bounds__(LANES)
+k_small_qr(double *H, int ldh, int off, int m, double hnorm, double smlnum, int maxit, double *Ut, int ldut,
+           int *status) {
+    extern __shared__ double lds[];
+    const int ld = m + 1;
+    double *T = lds;
+    double *Q = lds + (size_t)m * ld;
+    lds_load_block(H, ldh, off, m, T, ld, Q, ld);
+    int iters = 0;
+    int info = lds_small_qr(T, ld, Q, ld, m, hnorm, smlnum, maxit, &iters);
+    __syncthreads();
+    lds_store(H, ldh, off, m, T, ld, Q, ld, Ut, ldut);
+    if (threadIdx.x == 0) {
+        status[0] = info;
+        status[1] = iters;
+    }
+}
+
+// ---------------------------------------------------------------- block swap
+//
+// Swapping adjacent diagonal blocks A (p x p, on top) and C (q x q) of a
+// quasi-triangular matrix [[A B][0 C]]: solve A X - X C = B; the columns of
+// [[-X][I]] span C's invariant subspace, so the orthogonal factor Q of their QR
+// factorisation gives Q^T [[A B][0 C]] Q = [[C' *][0 A']].  The swap is
+// rejected when the computed lower-left block or the reconstruction error is
+// not at roundoff level.  Sizes are template parameters so that every array
+// below has constant indices and lives in registers.
+
+// Solve the K x K system M x = r by Gaussian elimination with complete
+// pivoting; row and column exchanges are done with selects.  Tiny pivots are
+// raised to smin.
+template <int K>
+__device__ __forceinline__ bool solve_cp(double (&M)[K][K], double (&r)[K], double (&x)[K]) {
+    int perm[K];
+    double mx = 0.0;
+#pragma unroll
+    for (int i = 0; i < K; ++i) {
+        perm[i] = i;
+#pragma unroll
+        for (int j = 0; j < K; ++j) mx = fmax(mx, fabs(M[i][j]));
+    }
+    const double smin = fmax(NEIG_EPS * mx, NEIG_DBL_MIN);
+#pragma unroll
+    for (int s = 0; s < K; ++s) {
+        int pr = s, pc = s;
+        double best = -1.0;
+#pragma unroll
+        for (int i = s; i < K; ++i)
+#pragma unroll
+            for (int j = s; j < K; ++j) {
+                const double v = fabs(M[i][j]);
+                if (v > best) { best = v; pr = i; pc = j; }
+            }
+#pragma unroll
+        for (int i = s + 1; i < K; ++i) {
+            const bool sw = (i == pr);
+#pragma unroll
+            for (int j = 0; j < K; ++j) {
+                const double a = M[s][j], b = M[i][j];
+                M[s][j] = sw ? b : a;
+                M[i][j] = sw ? a : b;
+            }
+            const double a = r[s], b = r[i];
+            r[s] = sw ? b : a;
+            r[i] = sw ? a : b;
+        }
+#pragma unroll
+        for (int j = s + 1; j < K; ++j) {
+            const bool sw = (j == pc);
+#pragma unroll
+            for (int i = 0; i < K; ++i) {
+                const double a = M[i][s], b = M[i][j];
+                M[i][s] = sw ? b : a;
+                M[i][j] = sw ? a : b;
+            }
+            const int pa = perm[s], pb = perm[j];
+            perm[s] = sw ? pb : pa;
+            perm[j] = sw ? pa : pb;
+        }
+        if (fabs(M[s][s]) < smin) M[s][s] = smin;
+#pragma unroll
+        for (int i = s + 1; i < K; ++i) {
+            const double f = M[i][s] / M[s][s];
+#pragma unroll
+            for (int j = s; j < K; ++j) M[i][j] -= f * M[s][j];
+            r[i] -= f * r[s];
+        }
+    }
+    double y[K];
+#pragma unroll
+    for (int s = K - 1; s >= 0; --s) {
+        double t = r[s];
+#pragma unroll
+        for (int j = s + 1; j < K; ++j) t -= M[s][j] * y[j];
+        y[s] = t / M[s][s];
+    }
+    bool ok = true;
+#pragma unroll
+    for (int i = 0; i < K; ++i) {
+        double v = 0.0;
+#pragma unroll
+        for (int s = 0; s < K; ++s) v = (perm[s] == i) ? y[s] : v;
+        x[i] = v;
+        ok = ok && isfinite(v);
+    }
+    return ok;
+}
+
+// Orthogonal Qm (N x N) and the swapped block Bn = Qm^T B Qm for block sizes (P, Q).
+template <int P, int Q>
+__device__ __forceinline__ bool swap_transform(const double (&B)[P + Q][P + Q], double (&Qm)[P + Q][P + Q],
+                                               double (&Bn)[P + Q][P + Q]) {
+    constexpr int N = P + Q;
+    double bnorm = 0.0;
+#pragma unroll
+    for (int i = 0; i < N; ++i)
+#pragma unroll
+        for (int j = 0; j < N; ++j) bnorm = fmax(bnorm, fabs(B[i][j]));
+    bnorm *= N;  // >= Frobenius norm
+#pragma unroll
+    for (int i = 0; i < N; ++i)
+#pragma unroll
+        for (int j = 0; j < N; ++j) Qm[i][j] = (i == j) ? 1.0 : 0.0;
+    if constexpr (P == 1 && Q == 1) {
+        const double a = B[0][0], b = B[0][1], c = B[1][1];
+        const double x0 = b, x1 = c - a;
+        if (x0 == 0.0 && x1 == 0.0) {
+#pragma unroll
+            for (int i = 0; i < N; ++i)
+#pragma unroll
+                for (int j = 0; j < N; ++j) Bn[i][j] = B[i][j];
+            return true;
+        }
+        const double rr = hypot(x0, x1);
+        const double cs = x0 / rr, sn = x1 / rr;
+        Qm[0][0] = cs; Qm[1][0] = sn; Qm[0][1] = -sn; Qm[1][1] = cs;
+        Bn[0][0] = c; Bn[0][1] = b; Bn[1][0] = 0.0; Bn[1][1] = a;
+        return true;
+    } else {
+        constexpr int K = P * Q;
+        double M[K][K], rhs[K], X[K];
+#pragma unroll
+        for (int i = 0; i < K; ++i)
+#pragma unroll
+            for (int j = 0; j < K; ++j) M[i][j] = 0.0;
+        // unknown X(i, j) at index i + P j; equation (i, j): sum_k A(i,k) X(k,j) - sum_k X(i,k) C(k,j) = B(i, P+j)
+#pragma unroll
+        for (int j = 0; j < Q; ++j)
+#pragma unroll
+            for (int i = 0; i < P; ++i) {
+                const int row = i + P * j;
+                rhs[row] = B[i][P + j];
+#pragma unroll
+                for (int k = 0; k < P; ++k) M[row][k + P * j] += B[i][k];
+#pragma unroll
+                for (int k = 0; k < Q; ++k) M[row][i + P * k] -= B[P + k][P + j];
+            }
+        if (!solve_cp<K>(M, rhs, X)) return false;
+        double xm = 0.0;
+#pragma unroll
+        for (int t = 0; t < K; ++t) xm = fmax(xm, fabs(X[t]));
+        const double g = 1.0 / fmax(1.0, xm);
+        double Y[N][Q];
+#pragma unroll
+        for (int j = 0; j < Q; ++j)
+#pragma unroll
+            for (int i = 0; i < N; ++i) Y[i][j] = (i < P) ? -g * X[i + P * j] : ((i - P == j) ? g : 0.0);
+        // Householder QR of Y, reflectors accumulated into Qm
+#pragma unroll
+        for (int c = 0; c < Q; ++c) {
+            double v[N];
+#pragma unroll
+            for (int t = 0; t < N; ++t) v[t] = (t >= c) ? Y[t][c] : 0.0;
+            double mx = 0.0;
+#pragma unroll
+            for (int t = c + 1; t < N; ++t) mx = fmax(mx, fabs(v[t]));
+            if (mx == 0.0) continue;
+            const double sc = fmax(mx, fabs(v[c]));
+            double ss = 0.0;
+#pragma unroll
+            for (int t = c; t < N; ++t) ss += (v[t] / sc) * (v[t] / sc);
+            const double nrm = sc * sqrt(ss);
+            const double alpha = v[c];
+            const double beta = alpha >= 0.0 ? -nrm : nrm;
+            const double tau = (beta - alpha) / beta;
+            const double inv = 1.0 / (alpha - beta);
+#pragma unroll
+            for (int t = c + 1; t < N; ++t) v[t] *= inv;
+            v[c] = 1.0;
+#pragma unroll
+            for (int j = c; j < Q; ++j) {
+                double d = 0.0;
+#pragma unroll
+                for (int t = c; t < N; ++t) d += v[t] * Y[t][j];
+                d *= tau;
+#pragma unroll
+                for (int t = c; t < N; ++t) Y[t][j] -= d * v[t];
+            }
+#pragma unroll
+            for (int i = 0; i < N; ++i) {
+                double d = 0.0;
+#pragma unroll
+                for (int t = c; t < N; ++t) d += Qm[i][t] * v[t];
+                d *= tau;
+#pragma unroll
+                for (int t = c; t < N; ++t) Qm[i][t] -= d * v[t];
+            }
+        }
+        double W[N][N];
+#pragma unroll
+        for (int i = 0; i < N; ++i)
+#pragma unroll
+            for (int j = 0; j < N; ++j) {
+                double d = 0.0;
+#pragma unroll
+                for (int k = 0; k < N; ++k) d += B[i][k] * Qm[k][j];
+                W[i][j] = d;
+            }
+#pragma unroll
+        for (int i = 0; i < N; ++i)
+#pragma unroll
+            for (int j = 0; j < N; ++j) {
+                double d = 0.0;
+#pragma unroll
+                for (int k = 0; k < N; ++k) d += Qm[k][i] * W[k][j];
+                Bn[i][j] = d;
+            }
+        const double thresh = fmax(20.0 * NEIG_EPS * bnorm, NEIG_DBL_MIN);
+        double low = 0.0;
+#pragma unroll
+        for (int j = 0; j < Q; ++j)
+#pragma unroll
+            for (int i = Q; i < N; ++i) {
+                low = fmax(low, fabs(Bn[i][j]));
+                Bn[i][j] = 0.0;
+            }
+        if (!(low <= thresh)) return false;
+        // reconstruction: B ~ Qm Bn Qm^T
+#pragma unroll
+        for (int i = 0; i < N; ++i)
+#pragma unroll
+            for (int j = 0; j < N; ++j) {
+                double d = 0.0;
+#pragma unroll
+                for (int k = 0; k < N; ++k) d += Bn[i][k] * Qm[j][k];
+                W[i][j] = d;
+            }
+        double err = 0.0;
+#pragma unroll
+        for (int i = 0; i < N; ++i)
+#pragma unroll
+            for (int j = 0; j < N; ++j) {
+                double d = 0.0;
+#pragma unroll
+                for (int k = 0; k < N; ++k) d += Qm[i][k] * W[k][j];
+                err = fmax(err, fabs(d - B[i][j]));
+            }
+        return err <= thresh;
+    }
+}
+
+// Swap the adjacent diagonal blocks of T at st (sizes P then Q) in place, with
+// the transformation applied to whole rows/columns of the nw x nw window and to V.
+template <int P, int Q>
+__device__ bool lds_swap_pq(double *T, int ldt, double *V, int ldv, int nw, int st) {
+    constexpr int N = P + Q;
+    double B[N][N], Qm[N][N], Bn[N][N];
+#pragma unroll
+    for (int i = 0; i < N; ++i)
+#pragma unroll
+        for (int j = 0; j < N; ++j) B[i][j] = AT(T, ldt, st + i, st + j);
+    const bool ok = swap_transform<P, Q>(B, Qm, Bn);
+    __syncthreads();
+    if (!ok) return false;
+    for (int j = st + N + (int)threadIdx.x; j < nw; j += LANES) {
+        double o[N];
+#pragma unroll
+        for (int i = 0; i < N; ++i) o[i] = AT(T, ldt, st + i, j);
+#pragma unroll
+        for (int i = 0; i < N; ++i) {
+            double d = 0.0;
+#pragma unroll
+            for (int k = 0; k < N; ++k) d += Qm[k][i] * o[k];
+            AT(T, ldt, st + i, j) = d;
+        }
+    }
+    for (int i = (int)threadIdx.x; i < st + nw; i += LANES) {
+        double *M = (i < st) ? T : V;
+        const int ld = (i < st) ? ldt : ldv;
+        const int row = (i < st) ? i : i - st;
+        double o[N];
+#pragma unroll
+        for (int k = 0; k < N; ++k) o[k] = AT(M, ld, row, st + k);
+#pragma unroll
+        for (int j = 0; j < N; ++j) {
+            double d = 0.0;
+#pragma unroll
+            for (int k = 0; k < N; ++k) d += o[k] * Qm[k][j];
+            AT(M, ld, row, st + j) = d;
+        }
+    }
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int i = 0; i < N; ++i)
+#pragma unroll
+            for (int j = 0; j < N; ++j) AT(T, ldt, st + i, st + j) = Bn[i][j];
+    }
+    __syncthreads();
+    if (Q == 2 && AT(T, ldt, st + 1, st) != 0.0) lds_standardise(T, ldt, V, ldv, nw, st);
+    if (P == 2 && AT(T, ldt, st + Q + 1, st + Q) != 0.0) lds_standardise(T, ldt, V, ldv, nw, st + Q);
+    return true;
+}
+
+__device__ bool lds_swap(double *T, int ldt, double *V, int ldv, int nw, int st, int p, int q) {
+    if (p == 1 && q == 1) return lds_swap_pq<1, 1>(T, ldt, V, ldv, nw, st);
+    if (p == 1 && q == 2) return lds_swap_pq<1, 2>(T, ldt, V, ldv, nw, st);
+    if (p == 2 && q == 1) return lds_swap_pq<2, 1>(T, ldt, V, ldv, nw, st);
+    return lds_swap_pq<2, 2>(T, ldt, V, ldv, nw, st);
+}
+
+// ---------------------------------------------------------------- Householder helpers (vector in LDS)
+
+// Turn x[0..len-1] (LDS) into a Householder vector in place: on return
+// x[0] = 1, x[1..] = v, *tau and *beta set.  All lanes call.
+__device__ void lds_house(double *x, int len, double *tau, double *beta) {
+    const int lane = threadIdx.x;
+    double alpha = x[0];
+    double mx = 0.0;
+    for (int t = 1 + lane; t < len; t += LANES) mx = fmax(mx, fabs(x[t]));
+    mx = wave_max(mx);
+    if (mx == 0.0) {
+        *tau = 0.0;
+        *beta = alpha;
+        __syncthreads();
+        if (lane == 0) x[0] = 1.0;
+        __syncthreads();
+        return;
+    }
+    double sc = fmax(mx, fabs(alpha));
+    double ss = 0.0;
+    for (int t = 1 + lane; t < len; t += LANES) ss += (x[t] / sc) * (x[t] / sc);
+    ss = wave_sum(ss) + (alpha / sc) * (alpha / sc);
+    double nrm = sc * sqrt(ss);
+    double b = alpha >= 0.0 ? -nrm : nrm;
+    *tau = (b - alpha) / b;
+    *beta = b;
+    double inv = 1.0 / (alpha - b);
+    __syncthreads();
+    for (int t = 1 + lane; t < len; t += LANES) x[t] *= inv;
+    if (lane == 0) x[0] = 1.0;
+    __syncthreads();
+}
+
+// rows r0..r0+len-1 of M, columns c0..c1, from the left by I - tau v v^T
+__device__ void lds_refl_left(double *M, int ld, int r0, int len, int c0, int c1, double tau, const double *v) {
+    for (int j = c0 + (int)threadIdx.x; j <= c1; j += LANES) {
+        double d = 0.0;
+        for (int t = 0; t < len; ++t) d += v[t] * AT(M, ld, r0 + t, j);
+        d *= tau;
+        for (int t = 0; t < len; ++t) AT(M, ld, r0 + t, j) -= d * v[t];
+    }
+}
+
+// columns c0..c0+len-1 of M, rows r0..r1, from the right
+__device__ void lds_refl_right(double *M, int ld, int c0, int len, int r0, int r1, double tau, const double *v) {
+    for (int i = r0 + (int)threadIdx.x; i <= r1; i += LANES) {
+        double d = 0.0;
+        for (int t = 0; t < len; ++t) d += AT(M, ld, i, c0 + t) * v[t];
+        d *= tau;
+        for (int t = 0; t < len; ++t) AT(M, ld, i, c0 + t) -= d * v[t];
+    }
+}
+
+// ---------------------------------------------------------------- AED
+
+// status: [0] nd (deflated count), [1] number of Ritz values written to sr/si,
+// [2] 1 if H and the window transform V were updated (the host then applies V^T
+// to the rest of H and Z), [3] rows not converged by the window QR, [4] 1 if a
+// swap was rejected, [5] window QR iterations, [6] block swaps, [7..9] shader
+// clock cycles spent in the window QR, the spike test with its swaps, and the
+// re-Hessenberg reduction with the write-back.
+extern "C" __global__ void __launch_bounds__(LANES)
+k_aed(double *H, int ldh, int ktop, int kbot, int nw, double hnorm, double smlnum, int criterion, int maxit,
+      double *Vt, int ldvt, int *status, double *sr, double *si) {
+    extern __shared__ double lds[];
+    const int lane = threadIdx.x;
+    const int ld = nw + 1;
+    double *T = lds;
+    double *V = lds + (size_t)nw * ld;
+    double *x = V + (size_t)nw * ld;  // nw doubles of vector scratch
+    const int kwtop = kbot - nw + 1;
+    const double s = (kwtop > ktop) ? AT(H, ldh, kwtop, kwtop - 1) : 0.0;
+    const long long c0 = clock64();
+    lds_load_block(H, ldh, kwtop, nw, T, ld, V, ld);
+    int iters = 0;
+    const int infqr = lds_small_qr(T, ld, V, ld, nw, hnorm, smlnum, maxit, &iters);
+    __syncthreads();
+    const long long c1 = clock64();
+    int nswap = 0;
+
+    // spike test from the bottom up; failures move to [infqr, top)
+    int top = infqr, kend = nw, swapfail = 0;
+    while (kend > top) {
+        const int bs = (kend - 2 >= top && AT(T, ld, kend - 1, kend - 2) != 0.0) ? 2 : 1;
+        const int j = kend - bs;
+        double sp = fabs(s * AT(V, ld, 0, j));
+        if (bs == 2) sp = fmax(sp, fabs(s * AT(V, ld, 0, j + 1)));
+        double tol;
+        if (criterion == 1) {
+            tol = NEIG_EPS * hnorm;
+        } else {
+            double lam = (bs == 1) ? fabs(AT(T, ld, j, j))
+                                   : sqrt(fabs(AT(T, ld, j, j) * AT(T, ld, j + 1, j + 1) -
+                                               AT(T, ld, j, j + 1) * AT(T, ld, j + 1, j)));
+            if (lam == 0.0) lam = fabs(s);
+            tol = NEIG_EPS * lam;
+        }
+        tol = fmax(tol, smlnum);
+        if (sp <= tol) {
+            kend -= bs;
+            continue;
+        }
+        int pos = j;
+        bool ok = true;
+        while (pos > top) {
+            const int ba = (pos - 2 >= top && AT(T, ld, pos - 1, pos - 2) != 0.0) ? 2 : 1;
+            const int st = pos - ba;
+            if (!lds_swap(T, ld, V, ld, nw, st, ba, bs)) {
+                ok = false;
+                break;
+            }
+            ++nswap;
+            pos = st;
+        }
+        if (!ok) {
+            swapfail = 1;
+            top = kend;
+            break;
+        }
+        top += bs;
+    }
+    const int nd = nw - kend;
+    const long long c2 = clock64();
+
+    // undeflated Ritz values (shift candidates), top to bottom
+    if (lane == 0) {
+        int c = 0;
+        for (int j = infqr; j < kend;) {
+            if (j + 1 < kend && AT(T, ld, j + 1, j) != 0.0) {
+                double r1, i1, r2, i2;
+                eig2x2(AT(T, ld, j, j), AT(T, ld, j, j + 1), AT(T, ld, j + 1, j), AT(T, ld, j + 1, j + 1), &r1, &i1,
+                       &r2, &i2);
+                sr[c] = r1; si[c] = i1; sr[c + 1] = r2; si[c + 1] = i2;
+                c += 2;
+                j += 2;
+            } else {
+                sr[c] = AT(T, ld, j, j);
+                si[c] = 0.0;
+                ++c;
+                ++j;
+            }
+        }
+        status[0] = nd;
+        status[1] = c;
+        status[2] = (nd > 0) ? 1 : 0;
+        status[3] = infqr;
+        status[4] = swapfail;
+        status[5] = iters;
+        status[6] = nswap;
+        status[7] = (int)min(c1 - c0, (long long)INT_MAX);
+        status[8] = (int)min(c2 - c1, (long long)INT_MAX);
+        status[9] = 0;
+    }
+    if (nd == 0) return;  // H untouched; only the shifts are used
+
+    double spike0 = 0.0;
+    if (kend > 0 && s != 0.0) {
+        for (int t = lane; t < kend; t += LANES) x[t] = s * AT(V, ld, 0, t);
+        __syncthreads();
+        if (kend > 1) {
+            double tau, beta;
+            lds_house(x, kend, &tau, &beta);
+            spike0 = beta;
+            if (tau != 0.0) {
+                lds_refl_left(T, ld, 0, kend, 0, nw - 1, tau, x);
+                __syncthreads();
+                lds_refl_right(T, ld, 0, kend, 0, kend - 1, tau, x);
+                lds_refl_right(V, ld, 0, kend, 0, nw - 1, tau, x);
+                __syncthreads();
+            }
+            // Householder Hessenberg reduction of the undeflated leading block
+            for (int c = 0; c + 2 < kend; ++c) {
+                const int len = kend - c - 1;
+                for (int t = lane; t < len; t += LANES) x[t] = AT(T, ld, c + 1 + t, c);
+                __syncthreads();
+                double tau2, beta2;
+                lds_house(x, len, &tau2, &beta2);
+                if (tau2 == 0.0) continue;
+                for (int t = lane; t < len; t += LANES) AT(T, ld, c + 1 + t, c) = (t == 0) ? beta2 : 0.0;
+                lds_refl_left(T, ld, c + 1, len, c + 1, nw - 1, tau2, x);
+                __syncthreads();
+                lds_refl_right(T, ld, c + 1, len, 0, kend - 1, tau2, x);
+                lds_refl_right(V, ld, c + 1, len, 0, nw - 1, tau2, x);
+                __syncthreads();
+            }
+        } else {
+            spike0 = x[0];
+        }
+    }
+    __syncthreads();
+    lds_store(H, ldh, kwtop, nw, T, ld, V, ld, Vt, ldvt);
+    if (kwtop > ktop && lane == 0) {
+        AT(H, ldh, kwtop, kwtop - 1) = spike0;
+        status[9] = (int)min(clock64() - c2, (long long)INT_MAX);
+    }
+}
