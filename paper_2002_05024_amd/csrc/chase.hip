@@ -7,12 +7,14 @@
 // reflectors are applied from the left to the window's rows, from the right to
 // the window's columns, and accumulated into the window's orthogonal factor U.
 // Reflectors of one step act on disjoint index triples, so they commute and the
-// three phases are each fully parallel.  The window (and U) live in LDS; the
+// three phases are each fully parallel; 1024 threads give every thread only a
+// few (column, bulge) or (row, bulge) pairs, whose loads are all in flight
+// together.  The window (and U) live in LDS; the
 // kernel writes back the window and U^T, which the update kernels apply to the
 // rest of H and to Z (the left/right update tasks).
 #include "neig_dev.h"
 
-#define CHASE_THREADS 256
+#define CHASE_THREADS 1024
 #define CHASE_MAX_BULGES 32
 
 struct ChaseWin {
@@ -49,10 +51,14 @@ k_chase(double *H, int ldh, const double *poly, double *Ut, ChaseArgs a) {
     const int nb = W.nb;
     const double *mypoly = poly + 2 * (size_t)W.chain * a.nbc;
 
-    for (int j = 0; j < mb; ++j)
-        for (int i = tid; i < mb; i += CHASE_THREADS) AT(Hs, ldhs, i, j) = AT(H, ldh, b0 + i, b0 + j);
-    for (int j = 0; j < w; ++j)
-        for (int i = tid; i < w; i += CHASE_THREADS) AT(Us, ldus, i, j) = (i == j) ? 1.0 : 0.0;
+    for (int idx = tid; idx < mb * mb; idx += CHASE_THREADS) {
+        const int i = idx % mb, j = idx / mb;
+        AT(Hs, ldhs, i, j) = AT(H, ldh, b0 + i, b0 + j);
+    }
+    for (int idx = tid; idx < w * w; idx += CHASE_THREADS) {
+        const int i = idx % w, j = idx / w;
+        AT(Us, ldus, i, j) = (i == j) ? 1.0 : 0.0;
+    }
     __syncthreads();
 
     for (int t = W.t0; t < W.t1; ++t) {
@@ -96,84 +102,82 @@ k_chase(double *H, int ldh, const double *poly, double *Ut, ChaseArgs a) {
             }
         }
         __syncthreads();
-        // phase B: from the left, rows pos..pos+2 over columns pos..r1
+        // phase B: from the left, rows pos..pos+2 over columns pos..r1.  Thread
+        // (column jl, bulge group g) handles bulges g, g+8, g+16, g+24: their row
+        // triples are disjoint, so all loads are issued before any store.
         {
-            const int jl = tid & 127, half = tid >> 7;
+            const int jl = tid & 127, g = tid >> 7;
             if (jl < mb) {
                 const int j = b0 + jl;
-                for (int b = half; b < nb; b += 2) {
-                    const int pos = rpos[b];
-                    if (pos < 0 || pos > j) continue;
-                    const double tau = rtau[b];
-                    if (tau == 0.0) continue;
-                    const int p = pos - b0;
-                    const double v1 = rv1[b], v2 = rv2[b];
-                    if (rm3[b] == 3) {
-                        double x = AT(Hs, ldhs, p, jl), y = AT(Hs, ldhs, p + 1, jl), z = AT(Hs, ldhs, p + 2, jl);
-                        double s = tau * (x + v1 * y + v2 * z);
-                        AT(Hs, ldhs, p, jl) = x - s;
-                        AT(Hs, ldhs, p + 1, jl) = y - s * v1;
-                        AT(Hs, ldhs, p + 2, jl) = z - s * v2;
-                    } else {
-                        double x = AT(Hs, ldhs, p, jl), y = AT(Hs, ldhs, p + 1, jl);
-                        double s = tau * (x + v1 * y);
-                        AT(Hs, ldhs, p, jl) = x - s;
-                        AT(Hs, ldhs, p + 1, jl) = y - s * v1;
+                double x[4][3];
+                int pp[4];
+                bool act[4];
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const int b = g + 8 * q;
+                    const int pos = (b < nb) ? rpos[b] : -1;
+                    act[q] = pos >= 0 && pos <= j && rtau[b] != 0.0;
+                    pp[q] = pos - b0;
+                    if (act[q]) {
+                        x[q][0] = AT(Hs, ldhs, pp[q], jl);
+                        x[q][1] = AT(Hs, ldhs, pp[q] + 1, jl);
+                        x[q][2] = (rm3[b] == 3) ? AT(Hs, ldhs, pp[q] + 2, jl) : 0.0;
                     }
+                }
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    if (!act[q]) continue;
+                    const int b = g + 8 * q;
+                    const double tau = rtau[b], v1 = rv1[b], v2 = rv2[b];
+                    const double s = tau * (x[q][0] + v1 * x[q][1] + v2 * x[q][2]);
+                    AT(Hs, ldhs, pp[q], jl) = x[q][0] - s;
+                    AT(Hs, ldhs, pp[q] + 1, jl) = x[q][1] - s * v1;
+                    if (rm3[b] == 3) AT(Hs, ldhs, pp[q] + 2, jl) = x[q][2] - s * v2;
                 }
             }
         }
         __syncthreads();
-        // phase C: from the right, columns pos..pos+2 over rows b0..min(pos+3, kbot); and U
-        if (tid < 128) {
-            const int il = tid;
-            if (il < mb) {
-                const int i = b0 + il;
-                for (int b = 0; b < nb; ++b) {
-                    const int pos = rpos[b];
-                    if (pos < 0) continue;
-                    const int rmax = (pos + 3 < kbot) ? pos + 3 : kbot;
-                    if (i > rmax) continue;
-                    const double tau = rtau[b];
-                    if (tau == 0.0) continue;
-                    const int p = pos - b0;
-                    const double v1 = rv1[b], v2 = rv2[b];
-                    if (rm3[b] == 3) {
-                        double x = AT(Hs, ldhs, il, p), y = AT(Hs, ldhs, il, p + 1), z = AT(Hs, ldhs, il, p + 2);
-                        double s = tau * (x + v1 * y + v2 * z);
-                        AT(Hs, ldhs, il, p) = x - s;
-                        AT(Hs, ldhs, il, p + 1) = y - s * v1;
-                        AT(Hs, ldhs, il, p + 2) = z - s * v2;
-                    } else {
-                        double x = AT(Hs, ldhs, il, p), y = AT(Hs, ldhs, il, p + 1);
-                        double s = tau * (x + v1 * y);
-                        AT(Hs, ldhs, il, p) = x - s;
-                        AT(Hs, ldhs, il, p + 1) = y - s * v1;
+        // phase C: from the right, columns pos..pos+2 over rows b0..min(pos+3, kbot),
+        // and the same columns of U over all its rows.  Thread (row slot, bulge
+        // group g) handles bulges g, g+4, ..., g+28 (disjoint column triples).
+        {
+            const int slot = tid & 255, g = tid >> 8;
+            const bool isH = slot < 128;
+            const int il = isH ? slot : slot - 128;
+            if (isH ? (il < mb) : (il < w)) {
+                double *M = isH ? Hs : Us;
+                const int ldm = isH ? ldhs : ldus;
+                const int cbase = isH ? b0 : r0;
+                const int gi = b0 + il;  // global row (H only)
+                double x[8][3];
+                int pc[8];
+                bool act[8];
+#pragma unroll
+                for (int q = 0; q < 8; ++q) {
+                    const int b = g + 4 * q;
+                    const int pos = (b < nb) ? rpos[b] : -1;
+                    bool a = pos >= 0 && rtau[b] != 0.0;
+                    if (a && isH) {
+                        const int rmax = (pos + 3 < kbot) ? pos + 3 : kbot;
+                        a = gi <= rmax;
+                    }
+                    act[q] = a;
+                    pc[q] = pos - cbase;
+                    if (a) {
+                        x[q][0] = AT(M, ldm, il, pc[q]);
+                        x[q][1] = AT(M, ldm, il, pc[q] + 1);
+                        x[q][2] = (rm3[b] == 3) ? AT(M, ldm, il, pc[q] + 2) : 0.0;
                     }
                 }
-            }
-        } else {
-            const int iu = tid - 128;
-            if (iu < w) {
-                for (int b = 0; b < nb; ++b) {
-                    const int pos = rpos[b];
-                    if (pos < 0) continue;
-                    const double tau = rtau[b];
-                    if (tau == 0.0) continue;
-                    const int p = pos - r0;
-                    const double v1 = rv1[b], v2 = rv2[b];
-                    if (rm3[b] == 3) {
-                        double x = AT(Us, ldus, iu, p), y = AT(Us, ldus, iu, p + 1), z = AT(Us, ldus, iu, p + 2);
-                        double s = tau * (x + v1 * y + v2 * z);
-                        AT(Us, ldus, iu, p) = x - s;
-                        AT(Us, ldus, iu, p + 1) = y - s * v1;
-                        AT(Us, ldus, iu, p + 2) = z - s * v2;
-                    } else {
-                        double x = AT(Us, ldus, iu, p), y = AT(Us, ldus, iu, p + 1);
-                        double s = tau * (x + v1 * y);
-                        AT(Us, ldus, iu, p) = x - s;
-                        AT(Us, ldus, iu, p + 1) = y - s * v1;
-                    }
+#pragma unroll
+                for (int q = 0; q < 8; ++q) {
+                    if (!act[q]) continue;
+                    const int b = g + 4 * q;
+                    const double tau = rtau[b], v1 = rv1[b], v2 = rv2[b];
+                    const double s = tau * (x[q][0] + v1 * x[q][1] + v2 * x[q][2]);
+                    AT(M, ldm, il, pc[q]) = x[q][0] - s;
+                    AT(M, ldm, il, pc[q] + 1) = x[q][1] - s * v1;
+                    if (rm3[b] == 3) AT(M, ldm, il, pc[q] + 2) = x[q][2] - s * v2;
                 }
             }
         }
@@ -183,10 +187,14 @@ k_chase(double *H, int ldh, const double *poly, double *Ut, ChaseArgs a) {
     // write back what the window changed: columns r0..r1 (rows b0..r1), the three
     // entries of column b0 below r0, and U^T
     const int off = r0 - b0;
-    for (int jl = off; jl < mb; ++jl)
-        for (int il = tid; il < mb; il += CHASE_THREADS) AT(H, ldh, b0 + il, b0 + jl) = AT(Hs, ldhs, il, jl);
+    for (int idx = tid; idx < mb * (mb - off); idx += CHASE_THREADS) {
+        const int il = idx % mb, jl = off + idx / mb;
+        AT(H, ldh, b0 + il, b0 + jl) = AT(Hs, ldhs, il, jl);
+    }
     if (off == 1 && r0 > ktop && tid < 3 && tid + 1 < mb) AT(H, ldh, r0 + tid, b0) = AT(Hs, ldhs, 1 + tid, 0);
     double *Uo = Ut + (size_t)blockIdx.x * a.ldut * a.ldut;
-    for (int c = 0; c < w; ++c)
-        for (int r = tid; r < w; r += CHASE_THREADS) AT(Uo, a.ldut, r, c) = AT(Us, ldus, c, r);
+    for (int idx = tid; idx < w * w; idx += CHASE_THREADS) {
+        const int r = idx % w, c = idx / w;
+        AT(Uo, a.ldut, r, c) = AT(Us, ldus, c, r);
+    }
 }

@@ -293,7 +293,7 @@ class Solver {
         const size_t lds = (size_t)2 * m * (m + 1) * sizeof(double);
         const int maxit = 30 * std::max(10, m);
         timed(kSmall, [&] {
-            hipLaunchKernelGGL(k_small_qr, dim3(1), dim3(64), lds, st_, H_, ldh_, ktop, m, hnorm_, smlnum_, maxit,
+            hipLaunchKernelGGL(k_small_qr, dim3(1), dim3(NT), lds, st_, H_, ldh_, ktop, m, hnorm_, smlnum_, maxit,
                                ws_.vt, m, ws_.ist);
             ck(hipGetLastError());
         });
@@ -322,7 +322,7 @@ class Solver {
         const size_t lds = (size_t)(2 * nw * (nw + 1) + nw) * sizeof(double);
         const int maxit = 30 * std::max(10, nw);
         timed(kAed, [&] {
-            hipLaunchKernelGGL(k_aed, dim3(1), dim3(64), lds, st_, H_, ldh_, ktop, kbot, nw, hnorm_, smlnum_,
+            hipLaunchKernelGGL(k_aed, dim3(1), dim3(NT), lds, st_, H_, ldh_, ktop, kbot, nw, hnorm_, smlnum_,
                                p_.deflation, maxit, ws_.vt, nw, ws_.ist, ws_.dbuf, ws_.dbuf + nw);
             ck(hipGetLastError());
         });
@@ -509,15 +509,17 @@ class Solver {
         return out;
     }
 
+    // Defaults measured on MI355X for random Hessenberg input: the AED window QR is a
+    // latency-bound chain on one CU, so moderate windows deflate the most per unit time.
     int default_ns(int m) const {
-        int ns = p_.ns > 0 ? p_.ns : (m < 300 ? 16 : (m < 1000 ? 32 : 64));
+        int ns = p_.ns > 0 ? p_.ns : (m < 300 ? 16 : 32);
         ns = std::min(ns, std::max(2, m / 3));
         ns -= ns % 2;
         return std::max(ns, 2);
     }
 
     int default_nw(int m) const {
-        int nw = p_.nw > 0 ? p_.nw : std::max(32, default_ns(m) * 3 / 2);
+        int nw = p_.nw > 0 ? p_.nw : (m < 300 ? 48 : 64);
         nw = std::min(nw, nsmall_);
         return std::min(nw, m);
     }

@@ -7,21 +7,65 @@
 //  * k_aed: aggressive early deflation (Section 3.2, "AED step") on a trailing
 //    window that fits in LDS: window Schur form by the same QR, spike test of
 //    every diagonal block from the bottom up, failing blocks moved to the top of
-//    the window by swaps of adjacent diagonal blocks (Section 3.2, the
-//    Bai-Demmel block swap), then a Householder Hessenberg reduction of the
-//    remaining spike and undeflated part.
+//    the window by swaps of adjacent diagonal blocks (the Bai-Demmel block swap
+//    the paper cites), then a Householder Hessenberg reduction of the remaining
+//    spike and undeflated part.
 //
-// Both run as ONE wavefront (64 lanes): every LDS access of a step is issued by
-// the same wave, so the steps need no cross-wave barriers, and scalar decisions
-// are computed redundantly by all lanes from the same LDS values.
+// Four waves per workgroup.  In the QR iteration the chain of bulge steps is
+// latency-bound, so wave 0 runs it alone: each step updates only a near field
+// around the bulge (one pass: a mixed 4x3 block on lane 0, the columns to its
+// right and the rows above it on other lanes) and hands the next reflector's
+// input to every lane through a register broadcast.  Waves 1-3 meanwhile apply
+// the previous batch of FB reflectors to the far field (columns right of the
+// near field, rows above it, and the accumulated orthogonal factor).  Other
+// phases use all four waves with block barriers.
 #include "neig_dev.h"
 #include <climits>
 
-#define LANES 64
+#define NT 256     // threads per workgroup
+#define LANES 64   // wavefront size
+#define FB 16      // reflectors per near-field batch
+
+// Optional section timers (compiled in with -DNEIG_PROF): shader clock cycles
+// accumulated by thread 0 into g_prof[0..7].
+#ifdef NEIG_PROF
+__shared__ long long g_prof[8];
+#define PROF_T(v) const long long v = clock64()
+#define PROF_ADD(slot, t0) do { if (threadIdx.x == 0) g_prof[slot] += clock64() - (t0); } while (0)
+#else
+#define PROF_T(v)
+#define PROF_ADD(slot, t0) do { } while (0)
+#endif
+
+__device__ __forceinline__ double bcast_lane0(double v) {
+    const int lo = __builtin_amdgcn_readfirstlane(__double2loint(v));
+    const int hi = __builtin_amdgcn_readfirstlane(__double2hiint(v));
+    return __hiloint2double(hi, lo);
+}
+
+__device__ __forceinline__ void refl_apply3(double &a, double &b, double &c, double tau, double v1, double v2) {
+    const double t = tau * (a + v1 * b + v2 * c);
+    a -= t;
+    b -= t * v1;
+    c -= t * v2;
+}
+
+// Block-wide max / sum (all NT threads call; result in every thread).
+__device__ double block_reduce(double v, bool is_max) {
+    __shared__ double red[NT / LANES];
+    v = is_max ? wave_max(v) : wave_sum(v);
+    __syncthreads();
+    if ((threadIdx.x & (LANES - 1)) == 0) red[threadIdx.x / LANES] = v;
+    __syncthreads();
+    double r = red[0];
+#pragma unroll
+    for (int w = 1; w < NT / LANES; ++w) r = is_max ? fmax(r, red[w]) : r + red[w];
+    return r;
+}
 
 // rows r, r+1 of M, columns c0..c1: (x, y) <- (cs x + sn y, -sn x + cs y)
 __device__ __forceinline__ void lds_rot_rows(double *M, int ld, int r, int c0, int c1, double cs, double sn) {
-    for (int j = c0 + (int)threadIdx.x; j <= c1; j += LANES) {
+    for (int j = c0 + (int)threadIdx.x; j <= c1; j += NT) {
         double x = AT(M, ld, r, j), y = AT(M, ld, r + 1, j);
         AT(M, ld, r, j) = cs * x + sn * y;
         AT(M, ld, r + 1, j) = -sn * x + cs * y;
@@ -30,7 +74,7 @@ __device__ __forceinline__ void lds_rot_rows(double *M, int ld, int r, int c0, i
 
 // columns c, c+1 of M, rows r0..r1
 __device__ __forceinline__ void lds_rot_cols(double *M, int ld, int c, int r0, int r1, double cs, double sn) {
-    for (int i = r0 + (int)threadIdx.x; i <= r1; i += LANES) {
+    for (int i = r0 + (int)threadIdx.x; i <= r1; i += NT) {
         double x = AT(M, ld, i, c), y = AT(M, ld, i, c + 1);
         AT(M, ld, i, c) = cs * x + sn * y;
         AT(M, ld, i, c + 1) = -sn * x + cs * y;
@@ -54,66 +98,201 @@ __device__ void lds_standardise(double *T, int ldt, double *Q, int ldq, int m, i
     __syncthreads();
 }
 
-// One implicit double-shift step on the active rows l..i of the LDS matrix
-// (updates span the whole m x m matrix and Q's columns).
-__device__ void lds_francis(double *T, int ldt, double *Q, int ldq, int m, int l, int i, double tr, double det) {
+// Apply a batch of nb consecutive reflectors (positions k0..k0+nb-1) in order to
+// segments of the far field: columns c_lo..c_hi of T (rows k0..k0+nb+1), rows
+// 0..r_hi-1 of T (columns k0..k0+nb+1), and, if withq, every row of Q.  Work
+// items are spread over threads t0, t0+nth, ...  The coefficients are read into
+// registers once; segments of full length take a branch-free path.
+__device__ void far_apply(double *T, int ldt, double *Q, int ldq, int m, int k0, int nb, int c_lo, int c_hi,
+                          int r_hi, bool withq, const double *rt, const double *r1, const double *r2, int t0, int nth) {
+    const int ncol = (c_hi >= c_lo) ? c_hi - c_lo + 1 : 0;
+    const int total = ncol + r_hi + (withq ? m : 0);
+    if (t0 >= total) return;
+    const int len = (k0 + nb + 2 <= m) ? nb + 2 : m - k0;
+    double ct[FB], c1[FB], c2[FB];
+#pragma unroll
+    for (int t = 0; t < FB; ++t) {
+        const bool on = t < nb;
+        ct[t] = on ? rt[t] : 0.0;
+        c1[t] = on ? r1[t] : 0.0;
+        c2[t] = on ? r2[t] : 0.0;
+    }
+    const bool full = (len == FB + 2);
+    for (int it = t0; it < total; it += nth) {
+        double *base;
+        int stride;
+        if (it < ncol) {
+            base = &AT(T, ldt, k0, c_lo + it);
+            stride = 1;
+        } else if (it < ncol + r_hi) {
+            base = &AT(T, ldt, it - ncol, k0);
+            stride = ldt;
+        } else {
+            base = &AT(Q, ldq, it - ncol - r_hi, k0);
+            stride = ldq;
+        }
+        double x[FB + 2];
+        if (full) {
+#pragma unroll
+            for (int t = 0; t < FB + 2; ++t) x[t] = base[t * stride];
+#pragma unroll
+            for (int t = 0; t < FB; ++t) refl_apply3(x[t], x[t + 1], x[t + 2], ct[t], c1[t], c2[t]);
+#pragma unroll
+            for (int t = 0; t < FB + 2; ++t) base[t * stride] = x[t];
+        } else {
+#pragma unroll
+            for (int t = 0; t < FB + 2; ++t) x[t] = (t < len) ? base[t * stride] : 0.0;
+#pragma unroll
+            for (int t = 0; t < FB; ++t) refl_apply3(x[t], x[t + 1], x[t + 2], ct[t], c1[t], c2[t]);
+#pragma unroll
+            for (int t = 0; t < FB + 2; ++t)
+                if (t < len) base[t * stride] = x[t];
+        }
+    }
+}
+
+// One bulge step of near_steps for a fixed shape: M3 rows in the reflector and
+// RB = rmax - k + 1 rows in the mixed block (4: interior, 3: second to last,
+// 2: last step).  Every load is unconditional for the lane's role.
+template <int M3, int RB>
+__device__ __forceinline__ void near_step(double *T, int ldt, int l, int k, int k0, int cnear, double *rt, double *r1,
+                                          double *r2, double &x0, double &x1, double &x2) {
     const int lane = threadIdx.x;
-    for (int k = l; k <= i - 1; ++k) {
-        const int m3 = (k <= i - 2) ? 3 : 2;
-        double x0, x1, x2;
+    double blk[RB][M3];
+    double o[M3];
+    int cj = 0, rr = 0;
+    const bool isM = (lane == 0);
+    const bool isL = (lane >= 1 && lane < 32) && (k + M3 - 1 + lane <= cnear);
+    const bool isR = (lane >= 32) && (k0 + lane - 32 < k);
+    if (isM) {
+#pragma unroll
+        for (int a = 0; a < RB; ++a)
+#pragma unroll
+            for (int b = 0; b < M3; ++b) blk[a][b] = AT(T, ldt, k + a, k + b);
+    } else if (isL) {
+        cj = k + M3 - 1 + lane;
+#pragma unroll
+        for (int a = 0; a < M3; ++a) o[a] = AT(T, ldt, k + a, cj);
+    } else if (isR) {
+        rr = k0 + lane - 32;
+#pragma unroll
+        for (int b = 0; b < M3; ++b) o[b] = AT(T, ldt, rr, k + b);
+    }
+    Refl r = make_refl(x0, x1, (M3 == 3) ? x2 : 0.0);
+    const double v2 = (M3 == 3) ? r.v2 : 0.0;
+    double n0 = 0.0, n1 = 0.0, n2 = 0.0;
+    if (isM) {
+        rt[k - k0] = r.tau;
+        r1[k - k0] = r.v1;
+        r2[k - k0] = v2;
+#pragma unroll
+        for (int b = 0; b < M3; ++b) {
+            double c = (M3 == 3) ? blk[2][b] : 0.0;
+            refl_apply3(blk[0][b], blk[1][b], c, r.tau, r.v1, v2);
+            if (M3 == 3) blk[2][b] = c;
+        }
+#pragma unroll
+        for (int a = 0; a < RB; ++a) {
+            double c = (M3 == 3) ? blk[a][2] : 0.0;
+            refl_apply3(blk[a][0], blk[a][1], c, r.tau, r.v1, v2);
+            if (M3 == 3) blk[a][2] = c;
+        }
+#pragma unroll
+        for (int a = 0; a < RB; ++a)
+#pragma unroll
+            for (int b = 0; b < M3; ++b) AT(T, ldt, k + a, k + b) = blk[a][b];
+        if (k > l) {
+            AT(T, ldt, k, k - 1) = r.beta;
+            AT(T, ldt, k + 1, k - 1) = 0.0;
+            if (M3 == 3) AT(T, ldt, k + 2, k - 1) = 0.0;
+        }
+        if (RB > 1) n0 = blk[1][0];
+        if (RB > 2) n1 = blk[2][0];
+        if (RB > 3) n2 = blk[3][0];
+    } else if (isL) {
+        double c = (M3 == 3) ? o[M3 - 1] : 0.0;
+        refl_apply3(o[0], o[1], c, r.tau, r.v1, v2);
+        AT(T, ldt, k, cj) = o[0];
+        AT(T, ldt, k + 1, cj) = o[1];
+        if (M3 == 3) AT(T, ldt, k + 2, cj) = c;
+    } else if (isR) {
+        double c = (M3 == 3) ? o[M3 - 1] : 0.0;
+        refl_apply3(o[0], o[1], c, r.tau, r.v1, v2);
+        AT(T, ldt, rr, k) = o[0];
+        AT(T, ldt, rr, k + 1) = o[1];
+        if (M3 == 3) AT(T, ldt, rr, k + 2) = c;
+    }
+    // generating vector of step k+1: column k, rows k+1..k+3 (lane 0's block)
+    x0 = bcast_lane0(n0);
+    x1 = bcast_lane0(n1);
+    x2 = bcast_lane0(n2);
+}
+
+// Wave 0: bulge steps k0..k1-1 of the double-shift sweep on rows/cols l..i with
+// only the near field updated (columns up to cnear, rows from k0).  (x0, x1, x2)
+// carries the generating vector of the next step between calls.  Reflectors with
+// tau = 0 are exact no-ops, so no step is special-cased.
+__device__ void near_steps(double *T, int ldt, int l, int i, int k0, int k1, int cnear, double tr, double det,
+                           double *rt, double *r1, double *r2, double &x0, double &x1, double &x2) {
+    for (int k = k0; k < k1; ++k) {
         if (k == l) {
-            double h00 = AT(T, ldt, l, l), h01 = AT(T, ldt, l, l + 1);
-            double h10 = AT(T, ldt, l + 1, l), h11 = AT(T, ldt, l + 1, l + 1);
-            double h21 = AT(T, ldt, l + 2, l + 1);
+            const double h00 = AT(T, ldt, l, l), h01 = AT(T, ldt, l, l + 1);
+            const double h10 = AT(T, ldt, l + 1, l), h11 = AT(T, ldt, l + 1, l + 1);
+            const double h21 = AT(T, ldt, l + 2, l + 1);
             double sc = fmax(fmax(fabs(h00), fabs(h01)), fmax(fmax(fabs(h10), fabs(h11)), fabs(h21)));
             sc = fmax(sc, fmax(fabs(tr), sqrt(fabs(det))));
             if (sc == 0.0) sc = 1.0;
-            double a = h00 / sc, b = h01 / sc, c = h10 / sc, d = h11 / sc, e = h21 / sc;
-            double t = tr / sc, dt = det / (sc * sc);
+            const double rs = 1.0 / sc;
+            const double a = h00 * rs, b = h01 * rs, c = h10 * rs, d = h11 * rs, e = h21 * rs;
+            const double t = tr * rs, dt = det * rs * rs;
             x0 = a * a + b * c - t * a + dt;
             x1 = c * (a + d - t);
             x2 = c * e;
-        } else {
-            x0 = AT(T, ldt, k, k - 1);
-            x1 = AT(T, ldt, k + 1, k - 1);
-            x2 = (m3 == 3) ? AT(T, ldt, k + 2, k - 1) : 0.0;
         }
-        Refl r = make_refl(x0, x1, x2);
-        __syncthreads();
-        if (r.tau == 0.0) continue;
-        if (k > l && lane == 0) {
-            AT(T, ldt, k, k - 1) = r.beta;
-            AT(T, ldt, k + 1, k - 1) = 0.0;
-            if (m3 == 3) AT(T, ldt, k + 2, k - 1) = 0.0;
-        }
-        for (int j = k + lane; j < m; j += LANES) {
-            double a = AT(T, ldt, k, j), b = AT(T, ldt, k + 1, j);
-            double c = (m3 == 3) ? AT(T, ldt, k + 2, j) : 0.0;
-            double t = r.tau * (a + r.v1 * b + r.v2 * c);
-            AT(T, ldt, k, j) = a - t;
-            AT(T, ldt, k + 1, j) = b - t * r.v1;
-            if (m3 == 3) AT(T, ldt, k + 2, j) = c - t * r.v2;
-        }
-        __syncthreads();
-        const int rmax = (k + 3 < i) ? k + 3 : i;
-        for (int rr = lane; rr <= rmax; rr += LANES) {
-            double a = AT(T, ldt, rr, k), b = AT(T, ldt, rr, k + 1);
-            double c = (m3 == 3) ? AT(T, ldt, rr, k + 2) : 0.0;
-            double t = r.tau * (a + r.v1 * b + r.v2 * c);
-            AT(T, ldt, rr, k) = a - t;
-            AT(T, ldt, rr, k + 1) = b - t * r.v1;
-            if (m3 == 3) AT(T, ldt, rr, k + 2) = c - t * r.v2;
-        }
-        for (int rr = lane; rr < m; rr += LANES) {
-            double a = AT(Q, ldq, rr, k), b = AT(Q, ldq, rr, k + 1);
-            double c = (m3 == 3) ? AT(Q, ldq, rr, k + 2) : 0.0;
-            double t = r.tau * (a + r.v1 * b + r.v2 * c);
-            AT(Q, ldq, rr, k) = a - t;
-            AT(Q, ldq, rr, k + 1) = b - t * r.v1;
-            if (m3 == 3) AT(Q, ldq, rr, k + 2) = c - t * r.v2;
-        }
-        __syncthreads();
+        if (k + 3 <= i)
+            near_step<3, 4>(T, ldt, l, k, k0, cnear, rt, r1, r2, x0, x1, x2);
+        else if (k + 2 == i)
+            near_step<3, 3>(T, ldt, l, k, k0, cnear, rt, r1, r2, x0, x1, x2);
+        else
+            near_step<2, 2>(T, ldt, l, k, k0, cnear, rt, r1, r2, x0, x1, x2);
     }
+}
+
+// One implicit double-shift step (all NT threads call) on the active rows l..i
+// of the m x m LDS matrix T; updates span all of T and Q's columns.
+__device__ void lds_francis(double *T, int ldt, double *Q, int ldq, int m, int l, int i, double tr, double det) {
+    __shared__ double rq[2][3][FB];
+    const int tid = threadIdx.x, wave = tid / LANES;
+    double x0 = 0.0, x1 = 0.0, x2 = 0.0;
+    int pk0 = -1, pnb = 0, pcnear = 0, pb = 0, cb = 0;
+    for (int k0 = l; k0 <= i - 1; k0 += FB) {
+        const int k1 = (k0 + FB < i) ? k0 + FB : i;
+        const int cnear = (k1 + 1 < m - 1) ? k1 + 1 : m - 1;
+        if (wave == 0) {
+            PROF_T(pa);
+            if (pk0 >= 0 && cnear > pcnear)  // previous batch on the columns entering the near field
+                far_apply(T, ldt, Q, ldq, m, pk0, pnb, pcnear + 1, cnear, 0, false, rq[pb][0], rq[pb][1], rq[pb][2],
+                          tid, LANES);
+            near_steps(T, ldt, l, i, k0, k1, cnear, tr, det, rq[cb][0], rq[cb][1], rq[cb][2], x0, x1, x2);
+            PROF_ADD(0, pa);
+        } else if (pk0 >= 0) {
+            far_apply(T, ldt, Q, ldq, m, pk0, pnb, cnear + 1, m - 1, pk0, true, rq[pb][0], rq[pb][1], rq[pb][2],
+                      tid - LANES, NT - LANES);
+        }
+        PROF_T(pw);
+        __syncthreads();
+        PROF_ADD(1, pw);
+        pk0 = k0;
+        pnb = k1 - k0;
+        pcnear = cnear;
+        pb = cb;
+        cb ^= 1;
+    }
+    PROF_T(pf);
+    if (pk0 >= 0)
+        far_apply(T, ldt, Q, ldq, m, pk0, pnb, pcnear + 1, m - 1, pk0, true, rq[pb][0], rq[pb][1], rq[pb][2], tid, NT);
+    __syncthreads();
+    PROF_ADD(2, pf);
 }
 
 // Double-shift QR iteration on the m x m LDS matrix T (upper Hessenberg) with Q
@@ -121,23 +300,26 @@ __device__ void lds_francis(double *T, int ldt, double *Q, int ldq, int m, int l
 // maxit iterations.  *iters receives the iteration count.
 __device__ int lds_small_qr(double *T, int ldt, double *Q, int ldq, int m, double hnorm, double smlnum, int maxit,
                             int *iters) {
-    const int lane = threadIdx.x;
+    const int lane = threadIdx.x & (LANES - 1);
     int i = m - 1, its = 0, total = 0;
     while (i >= 0) {
+        PROF_T(pe);
         int l = 0;
         for (int base = i; base >= 1; base -= LANES) {
-            int k = base - lane;
+            const int k = base - lane;
             bool neg = false;
-            if (k >= 1) neg = negligible_sub(AT(T, ldt, k, k - 1), AT(T, ldt, k - 1, k - 1), AT(T, ldt, k, k), hnorm, smlnum);
-            unsigned long long mask = __ballot(neg);
+            if (k >= 1)
+                neg = negligible_sub(AT(T, ldt, k, k - 1), AT(T, ldt, k - 1, k - 1), AT(T, ldt, k, k), hnorm, smlnum);
+            const unsigned long long mask = __ballot(neg);
             if (mask) {
                 l = base - (__ffsll(mask) - 1);
                 break;
             }
         }
         __syncthreads();
-        if (l > 0 && lane == 0) AT(T, ldt, l, l - 1) = 0.0;
+        if (l > 0 && threadIdx.x == 0) AT(T, ldt, l, l - 1) = 0.0;
         __syncthreads();
+        PROF_ADD(3, pe);
         if (l == i) {
             --i;
             its = 0;
@@ -157,16 +339,17 @@ __device__ int lds_small_qr(double *T, int ldt, double *Q, int ldq, int m, doubl
         ++its;
         double tr, det;
         if (its == 10 || its == 20) {
-            double s = fabs(AT(T, ldt, i, i - 1)) + fabs(AT(T, ldt, i - 1, i - 2));
-            double x = AT(T, ldt, i, i);
+            const double s = fabs(AT(T, ldt, i, i - 1)) + fabs(AT(T, ldt, i - 1, i - 2));
+            const double x = AT(T, ldt, i, i);
             tr = 2.0 * x + 1.5 * s;
             det = x * x + 1.5 * s * x + s * s;
         } else {
-            double a = AT(T, ldt, i - 1, i - 1), b = AT(T, ldt, i - 1, i);
-            double c = AT(T, ldt, i, i - 1), d = AT(T, ldt, i, i);
+            const double a = AT(T, ldt, i - 1, i - 1), b = AT(T, ldt, i - 1, i);
+            const double c = AT(T, ldt, i, i - 1), d = AT(T, ldt, i, i);
             tr = a + d;
             det = a * d - b * c;
         }
+        __syncthreads();  // every wave has read the shift inputs before wave 0 writes
         lds_francis(T, ldt, Q, ldq, m, l, i, tr, det);
     }
     *iters = total;
@@ -176,11 +359,10 @@ __device__ int lds_small_qr(double *T, int ldt, double *Q, int ldq, int m, doubl
 // Load the m x m diagonal block of H at (off, off) into T (zeros below the
 // subdiagonal) and set Q = I.
 __device__ void lds_load_block(const double *H, int ldh, int off, int m, double *T, int ldt, double *Q, int ldq) {
-    for (int j = 0; j < m; ++j) {
-        for (int i = threadIdx.x; i < m; i += LANES) {
-            AT(T, ldt, i, j) = (i <= j + 1) ? AT(H, ldh, off + i, off + j) : 0.0;
-            AT(Q, ldq, i, j) = (i == j) ? 1.0 : 0.0;
-        }
+    for (int idx = threadIdx.x; idx < m * m; idx += NT) {
+        const int i = idx % m, j = idx / m;
+        AT(T, ldt, i, j) = (i <= j + 1) ? AT(H, ldh, off + i, off + j) : 0.0;
+        AT(Q, ldq, i, j) = (i == j) ? 1.0 : 0.0;
     }
     __syncthreads();
 }
@@ -188,29 +370,37 @@ __device__ void lds_load_block(const double *H, int ldh, int off, int m, double 
 // Write T back to H's diagonal block and Q^T to Ut (column-major, ld ldut).
 __device__ void lds_store(double *H, int ldh, int off, int m, const double *T, int ldt, const double *Q, int ldq,
                           double *Ut, int ldut) {
-    for (int j = 0; j < m; ++j) {
-        for (int i = threadIdx.x; i < m; i += LANES) {
-            AT(H, ldh, off + i, off + j) = (i <= j + 1) ? AT(T, ldt, i, j) : 0.0;
-            AT(Ut, ldut, i, j) = AT(Q, ldq, j, i);
-        }
+    for (int idx = threadIdx.x; idx < m * m; idx += NT) {
+        const int i = idx % m, j = idx / m;
+        AT(H, ldh, off + i, off + j) = (i <= j + 1) ? AT(T, ldt, i, j) : 0.0;
+        AT(Ut, ldut, i, j) = AT(Q, ldq, j, i);
     }
 }
 
-extern "C" __global__ void __launch_bounds__(LANES)
+extern "C" __global__ void __launch_bounds__(NT)
 k_small_qr(double *H, int ldh, int off, int m, double hnorm, double smlnum, int maxit, double *Ut, int ldut,
            int *status) {
     extern __shared__ double lds[];
     const int ld = m + 1;
     double *T = lds;
     double *Q = lds + (size_t)m * ld;
+#ifdef NEIG_PROF
+    if (threadIdx.x < 8) g_prof[threadIdx.x] = 0;
+    __syncthreads();
+    const long long p0 = clock64();
+#endif
     lds_load_block(H, ldh, off, m, T, ld, Q, ld);
     int iters = 0;
-    int info = lds_small_qr(T, ld, Q, ld, m, hnorm, smlnum, maxit, &iters);
+    const int info = lds_small_qr(T, ld, Q, ld, m, hnorm, smlnum, maxit, &iters);
     __syncthreads();
     lds_store(H, ldh, off, m, T, ld, Q, ld, Ut, ldut);
     if (threadIdx.x == 0) {
         status[0] = info;
         status[1] = iters;
+#ifdef NEIG_PROF
+        g_prof[7] = clock64() - p0;
+        for (int t = 0; t < 8; ++t) ((long long *)(status + 16))[t] = g_prof[t];
+#endif
     }
 }
 
@@ -470,31 +660,36 @@ __device__ bool lds_swap_pq(double *T, int ldt, double *V, int ldv, int nw, int 
     const bool ok = swap_transform<P, Q>(B, Qm, Bn);
     __syncthreads();
     if (!ok) return false;
-    for (int j = st + N + (int)threadIdx.x; j < nw; j += LANES) {
-        double o[N];
+    const int ncol = nw - (st + N);
+    const int total = ncol + st + nw;
+    for (int it = threadIdx.x; it < total; it += NT) {
+        if (it < ncol) {  // rows st..st+N-1 right of the pair: new = Qm^T old
+            const int j = st + N + it;
+            double o[N];
 #pragma unroll
-        for (int i = 0; i < N; ++i) o[i] = AT(T, ldt, st + i, j);
+            for (int i = 0; i < N; ++i) o[i] = AT(T, ldt, st + i, j);
 #pragma unroll
-        for (int i = 0; i < N; ++i) {
-            double d = 0.0;
+            for (int i = 0; i < N; ++i) {
+                double d = 0.0;
 #pragma unroll
-            for (int k = 0; k < N; ++k) d += Qm[k][i] * o[k];
-            AT(T, ldt, st + i, j) = d;
-        }
-    }
-    for (int i = (int)threadIdx.x; i < st + nw; i += LANES) {
-        double *M = (i < st) ? T : V;
-        const int ld = (i < st) ? ldt : ldv;
-        const int row = (i < st) ? i : i - st;
-        double o[N];
+                for (int k = 0; k < N; ++k) d += Qm[k][i] * o[k];
+                AT(T, ldt, st + i, j) = d;
+            }
+        } else {  // columns st..st+N-1 of the rows above (T) and of V: new = old Qm
+            const int i = it - ncol;
+            double *M = (i < st) ? T : V;
+            const int ld = (i < st) ? ldt : ldv;
+            const int row = (i < st) ? i : i - st;
+            double o[N];
 #pragma unroll
-        for (int k = 0; k < N; ++k) o[k] = AT(M, ld, row, st + k);
+            for (int k = 0; k < N; ++k) o[k] = AT(M, ld, row, st + k);
 #pragma unroll
-        for (int j = 0; j < N; ++j) {
-            double d = 0.0;
+            for (int j = 0; j < N; ++j) {
+                double d = 0.0;
 #pragma unroll
-            for (int k = 0; k < N; ++k) d += o[k] * Qm[k][j];
-            AT(M, ld, row, st + j) = d;
+                for (int k = 0; k < N; ++k) d += o[k] * Qm[k][j];
+                AT(M, ld, row, st + j) = d;
+            }
         }
     }
     if (threadIdx.x == 0) {
@@ -519,39 +714,38 @@ __device__ bool lds_swap(double *T, int ldt, double *V, int ldv, int nw, int st,
 // ---------------------------------------------------------------- Householder helpers (vector in LDS)
 
 // Turn x[0..len-1] (LDS) into a Householder vector in place: on return
-// x[0] = 1, x[1..] = v, *tau and *beta set.  All lanes call.
+// x[0] = 1, x[1..] = v, *tau and *beta set.  All NT threads call.
 __device__ void lds_house(double *x, int len, double *tau, double *beta) {
-    const int lane = threadIdx.x;
-    double alpha = x[0];
+    const double alpha = x[0];
     double mx = 0.0;
-    for (int t = 1 + lane; t < len; t += LANES) mx = fmax(mx, fabs(x[t]));
-    mx = wave_max(mx);
+    for (int t = 1 + (int)threadIdx.x; t < len; t += NT) mx = fmax(mx, fabs(x[t]));
+    mx = block_reduce(mx, true);
     if (mx == 0.0) {
         *tau = 0.0;
         *beta = alpha;
         __syncthreads();
-        if (lane == 0) x[0] = 1.0;
+        if (threadIdx.x == 0) x[0] = 1.0;
         __syncthreads();
         return;
     }
-    double sc = fmax(mx, fabs(alpha));
+    const double sc = fmax(mx, fabs(alpha));
     double ss = 0.0;
-    for (int t = 1 + lane; t < len; t += LANES) ss += (x[t] / sc) * (x[t] / sc);
-    ss = wave_sum(ss) + (alpha / sc) * (alpha / sc);
-    double nrm = sc * sqrt(ss);
-    double b = alpha >= 0.0 ? -nrm : nrm;
+    for (int t = 1 + (int)threadIdx.x; t < len; t += NT) ss += (x[t] / sc) * (x[t] / sc);
+    ss = block_reduce(ss, false) + (alpha / sc) * (alpha / sc);
+    const double nrm = sc * sqrt(ss);
+    const double b = alpha >= 0.0 ? -nrm : nrm;
     *tau = (b - alpha) / b;
     *beta = b;
-    double inv = 1.0 / (alpha - b);
+    const double inv = 1.0 / (alpha - b);
     __syncthreads();
-    for (int t = 1 + lane; t < len; t += LANES) x[t] *= inv;
-    if (lane == 0) x[0] = 1.0;
+    for (int t = 1 + (int)threadIdx.x; t < len; t += NT) x[t] *= inv;
+    if (threadIdx.x == 0) x[0] = 1.0;
     __syncthreads();
 }
 
 // rows r0..r0+len-1 of M, columns c0..c1, from the left by I - tau v v^T
 __device__ void lds_refl_left(double *M, int ld, int r0, int len, int c0, int c1, double tau, const double *v) {
-    for (int j = c0 + (int)threadIdx.x; j <= c1; j += LANES) {
+    for (int j = c0 + (int)threadIdx.x; j <= c1; j += NT) {
         double d = 0.0;
         for (int t = 0; t < len; ++t) d += v[t] * AT(M, ld, r0 + t, j);
         d *= tau;
@@ -559,13 +753,18 @@ __device__ void lds_refl_left(double *M, int ld, int r0, int len, int c0, int c1
     }
 }
 
-// columns c0..c0+len-1 of M, rows r0..r1, from the right
-__device__ void lds_refl_right(double *M, int ld, int c0, int len, int r0, int r1, double tau, const double *v) {
-    for (int i = r0 + (int)threadIdx.x; i <= r1; i += LANES) {
+// columns c0..c0+len-1 of M (rows r0..r1) and of M2 (rows 0..r2-1), from the right
+__device__ void lds_refl_right2(double *M, int ld, int r0, int r1, double *M2, int ld2, int r2, int c0, int len,
+                                double tau, const double *v) {
+    const int n1 = (r1 >= r0) ? r1 - r0 + 1 : 0;
+    for (int it = threadIdx.x; it < n1 + r2; it += NT) {
+        double *A = (it < n1) ? M : M2;
+        const int lda = (it < n1) ? ld : ld2;
+        const int i = (it < n1) ? r0 + it : it - n1;
         double d = 0.0;
-        for (int t = 0; t < len; ++t) d += AT(M, ld, i, c0 + t) * v[t];
+        for (int t = 0; t < len; ++t) d += AT(A, lda, i, c0 + t) * v[t];
         d *= tau;
-        for (int t = 0; t < len; ++t) AT(M, ld, i, c0 + t) -= d * v[t];
+        for (int t = 0; t < len; ++t) AT(A, lda, i, c0 + t) -= d * v[t];
     }
 }
 
@@ -577,11 +776,11 @@ __device__ void lds_refl_right(double *M, int ld, int c0, int len, int r0, int r
 // swap was rejected, [5] window QR iterations, [6] block swaps, [7..9] shader
 // clock cycles spent in the window QR, the spike test with its swaps, and the
 // re-Hessenberg reduction with the write-back.
-extern "C" __global__ void __launch_bounds__(LANES)
+extern "C" __global__ void __launch_bounds__(NT)
 k_aed(double *H, int ldh, int ktop, int kbot, int nw, double hnorm, double smlnum, int criterion, int maxit,
       double *Vt, int ldvt, int *status, double *sr, double *si) {
     extern __shared__ double lds[];
-    const int lane = threadIdx.x;
+    const int tid = threadIdx.x;
     const int ld = nw + 1;
     double *T = lds;
     double *V = lds + (size_t)nw * ld;
@@ -614,6 +813,7 @@ k_aed(double *H, int ldh, int ktop, int kbot, int nw, double hnorm, double smlnu
             tol = NEIG_EPS * lam;
         }
         tol = fmax(tol, smlnum);
+        __syncthreads();  // all threads have read the test inputs before any swap writes
         if (sp <= tol) {
             kend -= bs;
             continue;
@@ -641,14 +841,14 @@ k_aed(double *H, int ldh, int ktop, int kbot, int nw, double hnorm, double smlnu
     const long long c2 = clock64();
 
     // undeflated Ritz values (shift candidates), top to bottom
-    if (lane == 0) {
+    if (tid == 0) {
         int c = 0;
         for (int j = infqr; j < kend;) {
             if (j + 1 < kend && AT(T, ld, j + 1, j) != 0.0) {
-                double r1, i1, r2, i2;
-                eig2x2(AT(T, ld, j, j), AT(T, ld, j, j + 1), AT(T, ld, j + 1, j), AT(T, ld, j + 1, j + 1), &r1, &i1,
-                       &r2, &i2);
-                sr[c] = r1; si[c] = i1; sr[c + 1] = r2; si[c + 1] = i2;
+                double re1, im1, re2, im2;
+                eig2x2(AT(T, ld, j, j), AT(T, ld, j, j + 1), AT(T, ld, j + 1, j), AT(T, ld, j + 1, j + 1), &re1,
+                       &im1, &re2, &im2);
+                sr[c] = re1; si[c] = im1; sr[c + 1] = re2; si[c + 1] = im2;
                 c += 2;
                 j += 2;
             } else {
@@ -673,7 +873,7 @@ k_aed(double *H, int ldh, int ktop, int kbot, int nw, double hnorm, double smlnu
 
     double spike0 = 0.0;
     if (kend > 0 && s != 0.0) {
-        for (int t = lane; t < kend; t += LANES) x[t] = s * AT(V, ld, 0, t);
+        for (int t = tid; t < kend; t += NT) x[t] = s * AT(V, ld, 0, t);
         __syncthreads();
         if (kend > 1) {
             double tau, beta;
@@ -682,23 +882,21 @@ k_aed(double *H, int ldh, int ktop, int kbot, int nw, double hnorm, double smlnu
             if (tau != 0.0) {
                 lds_refl_left(T, ld, 0, kend, 0, nw - 1, tau, x);
                 __syncthreads();
-                lds_refl_right(T, ld, 0, kend, 0, kend - 1, tau, x);
-                lds_refl_right(V, ld, 0, kend, 0, nw - 1, tau, x);
+                lds_refl_right2(T, ld, 0, kend - 1, V, ld, nw, 0, kend, tau, x);
                 __syncthreads();
             }
             // Householder Hessenberg reduction of the undeflated leading block
             for (int c = 0; c + 2 < kend; ++c) {
                 const int len = kend - c - 1;
-                for (int t = lane; t < len; t += LANES) x[t] = AT(T, ld, c + 1 + t, c);
+                for (int t = tid; t < len; t += NT) x[t] = AT(T, ld, c + 1 + t, c);
                 __syncthreads();
                 double tau2, beta2;
                 lds_house(x, len, &tau2, &beta2);
                 if (tau2 == 0.0) continue;
-                for (int t = lane; t < len; t += LANES) AT(T, ld, c + 1 + t, c) = (t == 0) ? beta2 : 0.0;
+                for (int t = tid; t < len; t += NT) AT(T, ld, c + 1 + t, c) = (t == 0) ? beta2 : 0.0;
                 lds_refl_left(T, ld, c + 1, len, c + 1, nw - 1, tau2, x);
                 __syncthreads();
-                lds_refl_right(T, ld, c + 1, len, 0, kend - 1, tau2, x);
-                lds_refl_right(V, ld, c + 1, len, 0, nw - 1, tau2, x);
+                lds_refl_right2(T, ld, 0, kend - 1, V, ld, nw, c + 1, len, tau2, x);
                 __syncthreads();
             }
         } else {
@@ -707,7 +905,7 @@ k_aed(double *H, int ldh, int ktop, int kbot, int nw, double hnorm, double smlnu
     }
     __syncthreads();
     lds_store(H, ldh, kwtop, nw, T, ld, V, ld, Vt, ldvt);
-    if (kwtop > ktop && lane == 0) {
+    if (kwtop > ktop && tid == 0) {
         AT(H, ldh, kwtop, kwtop - 1) = spike0;
         status[9] = (int)min(clock64() - c2, (long long)INT_MAX);
     }
