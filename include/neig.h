@@ -68,6 +68,7 @@ typedef struct neig_stats {
     /* inside the AED kernel: window-QR iterations, block swaps, and shader clock
        cycles of its three phases (window QR; spike test and swaps; re-Hessenberg) */
     double aed_qr_iters, aed_swaps, aed_cyc_qr, aed_cyc_defl, aed_cyc_hess;
+    double aed_late;     /* deflations found above a block that failed the spike test */
 } neig_stats;
 
 /*

@@ -48,6 +48,7 @@ def _load():
     lib.neig_oracle_std2x2.argtypes = [_dp] * 10
     lib.neig_oracle_std2x2.restype = None
     lib.neig_oracle_cond.argtypes = [i, _dp, i, _dp]
+    lib.neig_oracle_cond_subset.argtypes = [i, _dp, i, ctypes.POINTER(ctypes.c_int), i, _dp]
     lib.neig_oracle_last_iterations.argtypes = []
     _lib = lib
     return lib
@@ -125,4 +126,19 @@ def cond(S):
     info = lib.neig_oracle_cond(n, _ptr(Sc), max(1, n), _ptr(out))
     if info != 0:
         raise ValueError(f"neig_oracle_cond: info={info}")
+    return out
+
+
+def cond_subset(S, idx):
+    """Condition numbers of the eigenvalues at the listed diagonal positions of a
+    quasi-triangular S (each O(n^2))."""
+    lib = _load()
+    Sc = _f64(S)
+    n = Sc.shape[0]
+    ix = np.ascontiguousarray(idx, dtype=np.int32)
+    out = np.zeros(ix.size)
+    info = lib.neig_oracle_cond_subset(n, _ptr(Sc), max(1, n), ix.ctypes.data_as(ctypes.POINTER(ctypes.c_int)),
+                                       int(ix.size), _ptr(out))
+    if info != 0:
+        raise ValueError(f"neig_oracle_cond_subset: info={info}")
     return out

@@ -374,7 +374,7 @@ static void rescale(double complex *x, int lo, int hi) {
  * containing j.  Capped at 1/eps.  2x2 blocks are recognised by a nonzero
  * subdiagonal entry.
  */
-int neig_oracle_cond(int n, const double *S, int lds, double *cond) {
+static int neig_oracle_cond_select(int n, const double *S, int lds, const int *idx, int nidx, double *cond) {
     if (n < 0) return -1;
     if (n == 0) return 0;
     double snorm = 0.0;
@@ -389,8 +389,18 @@ int neig_oracle_cond(int n, const double *S, int lds, double *cond) {
         if (i + 1 < n && EL(S, lds, i + 1, i) != 0.0) { bstart[i] = bstart[i + 1] = i; i += 2; }
         else { bstart[i] = i; i += 1; }
     }
+    char *want = (char *)calloc((size_t)n, 1);
+    if (idx) {
+        for (int t = 0; t < nidx; ++t)
+            if (idx[t] >= 0 && idx[t] < n) want[idx[t]] = 1;
+    }
     for (int j = 0; j < n;) {
         int bs = (j + 1 < n && EL(S, lds, j + 1, j) != 0.0) ? 2 : 1;
+        if (idx && !want[j] && !(bs == 2 && want[j + 1])) {
+            for (int t = 0; t < bs; ++t) cond[j + t] = 0.0;
+            j += bs;
+            continue;
+        }
         double complex lam;
         for (int i = 0; i < n; ++i) x[i] = w[i] = 0.0;
         int top = j + bs - 1; /* last row of the block */
@@ -462,6 +472,24 @@ int neig_oracle_cond(int n, const double *S, int lds, double *cond) {
         for (int t = 0; t < bs; ++t) cond[j + t] = c;
         j += bs;
     }
-    free(x); free(w); free(bstart);
+    free(x); free(w); free(bstart); free(want);
     return 0;
 }
+
+int neig_oracle_cond(int n, const double *S, int lds, double *cond) {
+    return neig_oracle_cond_select(n, S, lds, 0, 0, cond);
+}
+
+/*
+ * Condition numbers for selected diagonal positions only (each O(n^2)): for
+ * position j the block containing j is used; results in cond[0..nidx-1].
+ */
+int neig_oracle_cond_subset(int n, const double *S, int lds, const int *idx, int nidx, double *cond) {
+    if (n < 0 || nidx < 0) return -1;
+    double *all = (double *)malloc(sizeof(double) * (size_t)(n > 0 ? n : 1));
+    int rc = neig_oracle_cond_select(n, S, lds, idx, nidx, all);
+    for (int t = 0; t < nidx; ++t) cond[t] = all[idx[t]];
+    free(all);
+    return rc;
+}
+

@@ -73,6 +73,7 @@ class Stats(ctypes.Structure):
         ("aed_cyc_qr", ctypes.c_double),
         ("aed_cyc_defl", ctypes.c_double),
         ("aed_cyc_hess", ctypes.c_double),
+        ("aed_late", ctypes.c_double),
     ]
 
 

@@ -326,7 +326,7 @@ class Solver {
                                p_.deflation, maxit, ws_.vt, nw, ws_.ist, ws_.dbuf, ws_.dbuf + nw);
             ck(hipGetLastError());
         });
-        ck(hipMemcpyAsync(ws_.h_ist, ws_.ist, 10 * sizeof(int), hipMemcpyDeviceToHost, st_));
+        ck(hipMemcpyAsync(ws_.h_ist, ws_.ist, 12 * sizeof(int), hipMemcpyDeviceToHost, st_));
         ck(hipMemcpyAsync(ws_.h_dbuf, ws_.dbuf, 2 * nw * sizeof(double), hipMemcpyDeviceToHost, st_));
         sync_collect();
         const int nd = ws_.h_ist[0], nr = ws_.h_ist[1], applied = ws_.h_ist[2];
@@ -337,6 +337,7 @@ class Solver {
         stats_.aed_cyc_qr += ws_.h_ist[7];
         stats_.aed_cyc_defl += ws_.h_ist[8];
         if (applied) stats_.aed_cyc_hess += ws_.h_ist[9];
+        stats_.aed_late += ws_.h_ist[10];
         ritz.clear();
         for (int t = 0; t < nr; ++t) ritz.push_back({ws_.h_dbuf[t], ws_.h_dbuf[nw + t]});
         if (applied) {

@@ -28,17 +28,31 @@ struct Refl {
 
 __device__ __forceinline__ Refl make_refl(double x0, double x1, double x2) {
     Refl r;
-    double s = fabs(x1) + fabs(x2);
+    const double s = fabs(x1) + fabs(x2);
     if (s == 0.0) {
         r.tau = 0.0; r.v1 = 0.0; r.v2 = 0.0; r.beta = x0;
         return r;
     }
-    // scale before squaring so that neither overflow nor underflow spoils the norm
-    double sc = fmax(fabs(x0), s);
-    double a = x0 / sc, b = x1 / sc, c = x2 / sc;
-    double nrm = sc * sqrt(a * a + b * b + c * c);
-    double beta = (x0 >= 0.0) ? -nrm : nrm;
-    double inv = 1.0 / (x0 - beta);
+    const double mx = fmax(fabs(x0), s);
+    if (mx > 1e-150 && mx < 1e150) {
+        // no overflow or harmful underflow in the squares or in beta (x0 - beta);
+        // one division gives both 1/beta and 1/(x0 - beta)
+        const double nrm = sqrt(x0 * x0 + x1 * x1 + x2 * x2);
+        const double beta = (x0 >= 0.0) ? -nrm : nrm;
+        const double d = x0 - beta;
+        const double q = 1.0 / (beta * d);
+        const double inv = beta * q;  // 1 / (x0 - beta)
+        r.tau = -d * d * q;           // (beta - x0) / beta
+        r.v1 = x1 * inv;
+        r.v2 = x2 * inv;
+        r.beta = beta;
+        return r;
+    }
+    const double rs = 1.0 / mx;
+    const double a = x0 * rs, b = x1 * rs, c = x2 * rs;
+    const double nrm = mx * sqrt(a * a + b * b + c * c);
+    const double beta = (x0 >= 0.0) ? -nrm : nrm;
+    const double inv = 1.0 / (x0 - beta);
     r.tau = (beta - x0) / beta;
     r.v1 = x1 * inv;
     r.v2 = x2 * inv;

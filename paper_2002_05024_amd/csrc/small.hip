@@ -797,6 +797,7 @@ k_aed(double *H, int ldh, int ktop, int kbot, int nw, double hnorm, double smlnu
 
     // spike test from the bottom up; failures move to [infqr, top)
     int top = infqr, kend = nw, swapfail = 0;
+    int late = 0;  // deflations found after the first failure (they cost swaps)
     while (kend > top) {
         const int bs = (kend - 2 >= top && AT(T, ld, kend - 1, kend - 2) != 0.0) ? 2 : 1;
         const int j = kend - bs;
@@ -815,6 +816,7 @@ k_aed(double *H, int ldh, int ktop, int kbot, int nw, double hnorm, double smlnu
         tol = fmax(tol, smlnum);
         __syncthreads();  // all threads have read the test inputs before any swap writes
         if (sp <= tol) {
+            if (top > infqr) late += bs;
             kend -= bs;
             continue;
         }
@@ -868,6 +870,7 @@ k_aed(double *H, int ldh, int ktop, int kbot, int nw, double hnorm, double smlnu
         status[7] = (int)min(c1 - c0, (long long)INT_MAX);
         status[8] = (int)min(c2 - c1, (long long)INT_MAX);
         status[9] = 0;
+        status[10] = late;
     }
     if (nd == 0) return;  // H untouched; only the shifts are used
 

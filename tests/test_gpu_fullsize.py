@@ -1,0 +1,167 @@
+"""Parity at the workloads' full sizes, through the C ABI, in the same launch
+configuration the benchmark uses (library defaults).
+
+At these sizes the oracle cannot run whole; the checks are properties that hold
+at any size (backward error and orthogonality <= 50 n eps, exact structure and
+read-out, spectral invariants) plus, for the prescribed-spectrum matrices,
+eigenvalue parity against the prescribed spectrum on a sample whose condition
+numbers the oracle computes one by one from the prescribed T (an input, never
+a GPU result).
+"""
+import numpy as np
+import pytest
+
+import oracle
+from checks import EPS, eigs, match_eigenvalues, structure_violations
+from gpu_util import gpu_backward_error, gpu_orthogonality, say, to_dev, to_host
+from paper_2002_05024_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def neig():
+    import torch
+
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    from paper_2002_05024_amd import binding
+
+    binding.load_library()
+    return binding
+
+
+def structure_on_gpu(S):
+    """Exact zeros below the subdiagonal, checked on the device."""
+    import torch
+
+    return int(torch.count_nonzero(torch.tril(S, -2)).item())
+
+
+def prescribed_case(n, std_scale, idx):
+    g = inputs.rng(inputs.PRESCRIBED, idx)
+    T, lam = inputs.prescribed_quasi_triangular(n, g, std_scale)
+    U = inputs.haar_orthogonal(n, g)
+    A = np.asfortranarray(U @ T @ U.T)
+    H, Q1 = inputs.to_hessenberg(A)
+    return T, lam, A, H, Q1
+
+
+def t_eigs_in_order(T):
+    n = T.shape[0]
+    out = np.zeros(n, dtype=complex)
+    j = 0
+    while j < n:
+        if j + 1 < n and T[j + 1, j] != 0:
+            b = np.sqrt(abs(T[j, j + 1] * T[j + 1, j]))
+            out[j], out[j + 1] = T[j, j] + 1j * b, T[j, j] - 1j * b
+            j += 2
+        else:
+            out[j] = T[j, j]
+            j += 1
+    return out
+
+
+@pytest.mark.parametrize("variant", ["well_conditioned", "as_written"])
+def test_prescribed_spectrum_n4000(neig, variant):
+    n = 4000
+    std = 0.1 / np.sqrt(n) if variant == "well_conditioned" else 0.1
+    say(f"prescribed n={n} variant={variant}")
+    T, lam, A, H, Q1 = prescribed_case(n, std, 4000 if variant == "well_conditioned" else 4001)
+    Hd, Zd = to_dev(H), to_dev(Q1)
+    Ad = to_dev(A)
+    r = neig.schur(Hd, Zd)
+    assert r.info == 0
+    be = gpu_backward_error(Ad, Hd, r.Z)
+    oe = gpu_orthogonality(r.Z)
+    say(f"  backward(A) {be:.2e} orth {oe:.2e}")
+    assert be <= 50 * n * EPS and oe <= 50 * n * EPS
+    S = to_host(Hd)
+    wr, wi = r.wr.cpu().numpy(), r.wi.cpu().numpy()
+    assert structure_violations(S, wr, wi) == []
+    if variant == "as_written":
+        return  # eigenvalues of this T are not recoverable in FP64 (cond ~ 1/eps): parity unpinned
+    # eigenvalue parity against the prescribed spectrum on a sample
+    lt = t_eigs_in_order(T)
+    sample = np.sort(inputs.rng(inputs.PRESCRIBED, 4002).choice(n, 64, replace=False))
+    cond = oracle.cond_subset(T, sample)
+    got = eigs(wr, wi)
+    X, Y = match_eigenvalues(lt, got)
+    nh = np.linalg.norm(H)
+    for k, c in zip(sample, cond):
+        pos = int(np.argmin(np.abs(X - lt[k])))
+        assert abs(Y[pos] - lt[k]) <= 1e-10 * nh * c, (k, abs(Y[pos] - lt[k]), c)
+
+
+def test_random_hessenberg_n20000(neig):
+    """The benchmark's workload: backward error and orthogonality with GPU
+    products, exact structure, and the trace invariants of the input."""
+    import torch
+
+    import bench
+
+    n = 20000
+    say(f"random hessenberg n={n}")
+    H0 = bench.make_input(n, 0, torch.device("cuda:0"))
+    H = torch.empty_like(H0)
+    H.copy_(H0)
+    assert H.stride() == (1, n) and H.data_ptr() != H0.data_ptr()
+    r = neig.schur(H)
+    assert r.info == 0
+    be, oe = bench.backward_and_orth(H0, H, r.Z)
+    say(f"  backward {be:.2e} orth {oe:.2e}")
+    assert be <= 50 * n * EPS and oe <= 50 * n * EPS
+    assert structure_on_gpu(H) == 0
+    wr, wi = r.wr.cpu().numpy(), r.wi.cpu().numpy()
+    # standardised 2x2 blocks and exact read-out, checked on the diagonal band only
+    d = torch.diagonal(H).cpu().numpy()
+    sub = torch.diagonal(H, -1).cpu().numpy()
+    sup = torch.diagonal(H, 1).cpu().numpy()
+    assert not np.any((sub[:-1] != 0) & (sub[1:] != 0))
+    j = 0
+    while j < n:
+        if j + 1 < n and sub[j] != 0:
+            assert d[j] == d[j + 1] and sup[j] * sub[j] < 0
+            im = np.sqrt(abs(sup[j])) * np.sqrt(abs(sub[j]))
+            assert wr[j] == d[j] and wi[j] == im and wi[j + 1] == -im
+            j += 2
+        else:
+            assert wr[j] == d[j] and wi[j] == 0
+            j += 1
+    # invariants of the input: trace and trace(H^2) (exact formula for Hessenberg)
+    h0d = torch.diagonal(H0).cpu().numpy()
+    tr = h0d.sum()
+    tr2 = np.sum(h0d ** 2) + 2 * np.sum(torch.diagonal(H0, 1).cpu().numpy() * torch.diagonal(H0, -1).cpu().numpy())
+    nh = float(torch.linalg.norm(H0))
+    lam = wr + 1j * wi
+    assert abs(lam.sum() - tr) <= 50 * np.sqrt(n) * n * EPS * nh
+    assert abs((lam * lam).sum() - tr2) <= 50 * n * n * EPS * nh * nh
+
+
+def test_plain_n256_all_seeds(neig):
+    """The plain workload, all 32 seeds: full oracle parity at n = 256."""
+    from checks import backward_error, orthogonality
+
+    n = 256
+    worst = 0.0
+    unpinned = []
+    for seed in range(32):
+        H = inputs.random_hessenberg(n, inputs.rng(inputs.PLAIN, seed))
+        Hd = to_dev(H)
+        r = neig.schur(Hd)
+        assert r.info == 0
+        S, Z = to_host(Hd), to_host(r.Z)
+        wr, wi = r.wr.cpu().numpy(), r.wi.cpu().numpy()
+        assert backward_error(H, S, Z) <= 50 * n * EPS
+        assert orthogonality(Z) <= 50 * n * EPS
+        assert structure_violations(S, wr, wi) == []
+        S0, Z0, wr0, wi0, info0 = oracle.schur(H)
+        cnd = oracle.cond(S0)
+        order = np.lexsort((np.sign(wi0), np.abs(wi0), wr0))
+        A, B = match_eigenvalues(eigs(wr0, wi0), eigs(wr, wi))
+        c = cnd[order]
+        pinned = c * 1e-10 < 1
+        unpinned.append(float(np.mean(~pinned)))
+        err = np.abs(A - B)[pinned] / (np.linalg.norm(H) * c[pinned])
+        worst = max(worst, float(err.max()) if err.size else 0.0)
+        assert np.all(err <= 1e-10), seed
+    say(f"  worst scaled eigenvalue error {worst:.2e}; unpinned fraction mean {np.mean(unpinned):.2f}")

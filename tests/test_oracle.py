@@ -307,3 +307,41 @@ def test_cond_matches_lapack_eigenvectors():
     # pair the LAPACK cond values through the same matching
     idx = [int(np.argmin(np.abs(w - y))) for y in Y]
     assert np.allclose(c[order], cref[idx], rtol=1e-6)
+
+
+def test_cond_subset_matches_full():
+    T, _ = inputs.prescribed_quasi_triangular(70, inputs.rng(inputs.PRESCRIBED, 770), 0.1)
+    full = oracle.cond(T)
+    idx = [0, 3, 10, 11, 40, 69]
+    assert np.allclose(oracle.cond_subset(T, idx), full[idx], rtol=1e-12)
+
+
+def test_cond_of_prescribed_matrix_is_cond_of_t():
+    """Eigenvalue condition numbers are invariant under orthogonal similarity:
+    cond computed on the prescribed T equals cond computed on the oracle's Schur
+    form of U T U^T (same eigenvalue, matched)."""
+    n = 40
+    g = inputs.rng(inputs.PRESCRIBED, 771)
+    T, lam = inputs.prescribed_quasi_triangular(n, g, 0.1 / np.sqrt(n))
+    U = inputs.haar_orthogonal(n, g)
+    A = U @ T @ U.T
+    H, _ = oracle.hessenberg(A)
+    S, Z, wr, wi, info = oracle.schur(H)
+    cs = oracle.cond(S)
+    ct = oracle.cond(T)
+    lt = np.diag(T) + 1j * np.zeros(n)
+    # read T's eigenvalues in its diagonal order
+    j = 0
+    lt = np.zeros(n, dtype=complex)
+    while j < n:
+        if j + 1 < n and T[j + 1, j] != 0:
+            b = np.sqrt(abs(T[j, j + 1] * T[j + 1, j]))
+            lt[j], lt[j + 1] = T[j, j] + 1j * b, T[j, j] - 1j * b
+            j += 2
+        else:
+            lt[j] = T[j, j]
+            j += 1
+    ls = eigs(wr, wi)
+    for k in range(n):
+        m = int(np.argmin(np.abs(ls - lt[k])))
+        assert abs(cs[m] - ct[k]) <= 1e-6 * ct[k]
