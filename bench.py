@@ -10,8 +10,12 @@ solve and the final read-out).  Before each step, untimed, H is restored from a
 pristine device copy and Z reset to I.  W warm-up steps, then K timed steps,
 each bracketed by synchronisations; the reported value is the mean seconds per
 reduction.  The library's timing mode brackets each kernel launch with HIP
-events on the call's stream, which gives the live duration of the dominant
-kernel (the FP64-MFMA off-diagonal update) for the roofline figure.
+events on the call's stream, which gives the live per-launch durations behind
+the roofline figures: the dominant kernel on this input is the AED window
+kernel (a latency-bound FP64 chain on one CU per launch); the FP64-MFMA update
+kernel is reported beside it.  A second leg runs the batched workload (512
+problems of order 32..1024 in one graph-captured launch) and the same problems
+through the single-problem call.
 
 Prints one JSON line.
 """
@@ -25,6 +29,8 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 FP64_MFMA_PEAK_TFLOPS = 78.6   # MI355X dense FP64 matrix peak
+FP64_VECTOR_PEAK_TFLOPS = 78.6  # MI355X FP64 vector peak: 256 CUs x 128 flops/clock x 2.4 GHz
+CUS = 256
 HBM_PEAK_GBS = 8000.0
 
 
@@ -39,6 +45,11 @@ def parse():
     ap.add_argument("--check", type=int, default=1, help="backward error / orthogonality of the last step")
     ap.add_argument("--cpu-baseline", type=int, default=1)
     ap.add_argument("--cpu-n", type=int, default=1200, help="order of the oracle's bounded CPU sample")
+    ap.add_argument("--batched", type=int, default=1, help="also run the batched workload")
+    ap.add_argument("--batch-count", type=int, default=512)
+    ap.add_argument("--batch-steps", type=int, default=3)
+    ap.add_argument("--plain-loop", type=int, default=1, help="time the same batch solved one call at a time")
+    ap.add_argument("--single", type=int, default=1, help="run the n=20000 single-matrix workload")
     return ap.parse_args()
 
 
@@ -101,6 +112,165 @@ def cpu_baseline(n_sample, n_target):
     }
 
 
+KERNEL_SOURCES = {"k_aed": "small.hip", "k_small_qr": "small.hip", "k_update": "gemm.hip", "k_chase": "chase.hip"}
+
+
+def kernel_source_sha(kernel):
+    """Hash of the source file that defines ``kernel`` and the shared device
+    header: a counter summary holds only for the source it was taken on."""
+    import hashlib
+
+    csrc = os.path.join(ROOT, "paper_2002_05024_amd", "csrc")
+    h = hashlib.sha256()
+    for name in (KERNEL_SOURCES[kernel], "neig_dev.h"):
+        with open(os.path.join(csrc, name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def traffic_per_launch(kernel):
+    """HBM bytes per launch of ``kernel`` from the committed rocprofv3 counter
+    summary (FETCH_SIZE and WRITE_SIZE, each scaled by what it reads for a plain
+    copy of known size), or None when there is none for the current source."""
+    path = os.path.join(ROOT, "profiles", "hbm_traffic_n20000.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        rec = json.load(f)
+    k = rec.get("kernels", {}).get(kernel)
+    if not k or k.get("source_sha") != kernel_source_sha(kernel):
+        return None
+    return k["bytes_per_launch"]
+
+
+def rooflines(stats):
+    """Roofline figures of the kernels from the library's per-launch HIP event
+    timing: the dominant kernel (most GPU time) as ``roofline``, the others
+    beside it.  Algorithmic work per launch: k_aed 10 nw^3 flops (window Schur
+    form), k_update 2 w^2 len flops per task, k_chase the bytes of its windows
+    (load and store of the window of H, store of U)."""
+    aed_ms = sum(s["gpu_aed_ms"] for s in stats)
+    aed_n = sum(s["aeds"] for s in stats)
+    aed_fl = sum(s["aed_flops"] for s in stats)
+    upd_ms = sum(s["gpu_update_ms"] for s in stats)
+    upd_n = sum(s["n_update"] for s in stats)
+    upd_fl = sum(s["gemm_flops"] for s in stats)
+    out = {}
+    if aed_ms > 0:
+        ach = aed_fl / (aed_ms / 1000.0) / 1e12
+        tr = traffic_per_launch("k_aed")
+        out["roofline_aed"] = {
+            "kernel": "k_aed", "bound": "alu", "achieved": round(ach, 5), "peak": FP64_VECTOR_PEAK_TFLOPS,
+            "unit": "TFLOP/s", "frac": round(ach / FP64_VECTOR_PEAK_TFLOPS, 7),
+            "traffic": tr,
+            "avg_launch_us": round(aed_ms * 1000.0 / max(aed_n, 1), 1),
+            "flops_per_launch": round(aed_fl / max(aed_n, 1), 1),
+            "frac_of_one_cu": round(ach / (FP64_VECTOR_PEAK_TFLOPS / CUS), 5),
+        }
+    if upd_ms > 0:
+        ach = upd_fl / (upd_ms / 1000.0) / 1e12
+        out["roofline_update"] = {
+            "kernel": "k_update", "bound": "mfma", "achieved": round(ach, 3), "peak": FP64_MFMA_PEAK_TFLOPS,
+            "unit": "TFLOP/s", "frac": round(ach / FP64_MFMA_PEAK_TFLOPS, 4),
+            "traffic": traffic_per_launch("k_update"),
+            "avg_launch_us": round(upd_ms * 1000.0 / max(upd_n, 1), 2),
+            "flops_per_launch": round(upd_fl / max(upd_n, 1), 1),
+        }
+    dominant = "roofline_aed" if aed_ms >= upd_ms else "roofline_update"
+    if dominant in out:
+        out["roofline"] = dict(out[dominant])
+    return out
+
+
+def batched_leg(args, dev):
+    """The batched workload: ``batch_count`` problems with n uniform in [32, 1024],
+    half random N(0,1) Hessenberg and half prescribed-spectrum Hessenberg, Z from
+    I, all resident in HBM, solved by one neig_schur_batched launch captured in a
+    HIP graph.  Each timed step restores the inputs (untimed), then replays the
+    graph between two events.  Optionally the same problems are solved one by one
+    with neig_schur (the plain GPU form) for comparison."""
+    import numpy as np
+    import torch
+
+    from paper_2002_05024_amd import autotune, binding, inputs
+
+    t0 = time.perf_counter()
+    Hs, _ = inputs.batched_workload(args.batch_count, args.seed, threads=min(16, os.cpu_count() or 1))
+    sizes = np.array([h.shape[0] for h in Hs])
+    H0 = [torch.from_numpy(np.ascontiguousarray(h.T)).to(dev).t() for h in Hs]
+    del Hs
+    eye = [torch.eye(int(k), dtype=torch.float64, device=dev) for k in sizes]
+    tuned = autotune.apply_saved()
+    call = binding.batched_tables([torch.empty_like(h) for h in H0], [torch.empty_like(h) for h in H0])
+    print(f"[bench] batch of {len(sizes)} ready in {time.perf_counter() - t0:.1f}s (tuned table: {tuned})",
+          file=sys.stderr, flush=True)
+
+    def restore():
+        for a, b in zip(call.Hs, H0):
+            a.copy_(b)
+        for a, b in zip(call.Zs, eye):
+            a.copy_(b)
+        torch.cuda.synchronize()
+
+    restore()
+    binding.launch_batched(call)  # eager warm-up
+    torch.cuda.synchronize()
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph, stream=side):
+        binding.launch_batched(call, stream=side)
+    torch.cuda.synchronize()
+    times = []
+    for k in range(args.batch_steps):
+        restore()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        graph.replay()
+        e1.record()
+        torch.cuda.synchronize()
+        times.append(e0.elapsed_time(e1) / 1000.0)
+        print(f"[bench] batched step {k} {times[-1] * 1e3:.1f} ms", file=sys.stderr, flush=True)
+    info = call.info.cpu().numpy()
+    worst_be = worst_oe = 0.0
+    for h0, S, Z in zip(H0, call.Hs, call.Zs):
+        n = h0.shape[0]
+        R = torch.mm(torch.mm(Z, S), Z.t())
+        R.sub_(h0)
+        worst_be = max(worst_be, float(torch.linalg.norm(R) / torch.linalg.norm(h0)) / (n * 2.0 ** -52))
+        E = torch.mm(Z.t(), Z)
+        E.diagonal().sub_(1.0)
+        worst_oe = max(worst_oe, float(torch.linalg.norm(E)) / (n * 2.0 ** -52))
+    sec = sum(times) / len(times)
+    out = {
+        "workload": f"{len(sizes)} Hessenberg problems, n uniform in [32, 1024] (mean {sizes.mean():.0f}), "
+                    "half random N(0,1), half prescribed spectrum; Z from I; one graph-captured launch",
+        "solves_per_s": round(len(sizes) / sec, 2),
+        "ms_per_batch": round(sec * 1e3, 2),
+        "steps": args.batch_steps,
+        "all_converged": bool((info == 0).all()),
+        "worst_backward_error_over_n_eps": round(worst_be, 4),
+        "worst_orthogonality_over_n_eps": round(worst_oe, 4),
+        "tuned_table": tuned,
+    }
+    if args.plain_loop:
+        t_plain = 0.0
+        restore()
+        for i in range(len(sizes)):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            r = binding.schur(call.Hs[i], call.Zs[i])
+            e1.record()
+            torch.cuda.synchronize()
+            t_plain += e0.elapsed_time(e1) / 1000.0
+            if r.info != 0:
+                out["plain_unconverged"] = out.get("plain_unconverged", 0) + 1
+        out["plain_loop_solves_per_s"] = round(len(sizes) / t_plain, 2)
+        out["speedup_vs_plain_loop"] = round(t_plain / sec, 2)
+        print(f"[bench] plain loop {t_plain:.2f}s", file=sys.stderr, flush=True)
+    return out
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -113,6 +283,11 @@ def main():
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
     binding.load_library()
+    if not args.single:
+        line = {"metric": "Schur reduction seconds + FP64 GFLOP/s at n=20000; batched solves/sec",
+                "n_gpus": 1, "dtype": "f64", "data": "synthetic", "batched": batched_leg(args, dev)}
+        print(json.dumps(line), flush=True)
+        return
     n = args.n
     t_gen = time.perf_counter()
     H0 = make_input(n, args.seed, dev)
@@ -183,26 +358,16 @@ def main():
         "aed_cycles_M": {k: round(st[f"aed_cyc_{k}"] / 1e6, 1) for k in ("qr", "defl", "hess")},
     }
     if args.timing:
-        upd_ms = sum(s["gpu_update_ms"] for s in stats)
-        upd_n = sum(s["n_update"] for s in stats)
-        upd_flops = sum(s["gemm_flops"] for s in stats)
-        achieved = upd_flops / (upd_ms / 1000.0) / 1e12 if upd_ms > 0 else 0.0
-        line["roofline"] = {
-            "kernel": "k_update",
-            "bound": "mfma",
-            "achieved": round(achieved, 3),
-            "peak": FP64_MFMA_PEAK_TFLOPS,
-            "unit": "TFLOP/s",
-            "frac": round(achieved / FP64_MFMA_PEAK_TFLOPS, 4),
-            "traffic": None,
-            "avg_launch_us": round(upd_ms * 1000.0 / max(upd_n, 1), 2),
-            "flops_per_launch": round(upd_flops / max(upd_n, 1), 1),
-        }
+        line.update(rooflines(stats))
         line["gpu_ms_per_step"] = {k: round(sum(s[f"gpu_{k}_ms"] for s in stats) / len(stats), 1)
                                    for k in ("update", "chase", "aed", "small", "other")}
     if args.check:
         be, oe = backward_and_orth(H0, H, Z)
         line["check"] = {"backward_error": be, "orthogonality": oe, "bound_50n_eps": 50 * n * 2.0 ** -52}
+    if args.batched:
+        del H, Z, H0
+        torch.cuda.empty_cache()
+        line["batched"] = batched_leg(args, dev)
     if args.cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(args.cpu_n, n)
     print(json.dumps(line), flush=True)

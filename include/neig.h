@@ -50,7 +50,14 @@ typedef struct neig_params {
     int exc;       /* rounds without deflation before exceptional shifts                 */
     int timing;    /* 1: bracket every kernel launch with HIP events on the call's stream and
                       report per-kernel-class GPU time in neig_stats (adds host overhead) */
-    int reserved[6];
+    int policy;    /* shift count and deflation window per iteration:
+                      0: the default size rules;
+                      1: the proposal network installed by neig_policy_set, falling back to
+                         the default rules when it is not confident;
+                      2: exploration: uniformly random bins (seeded by `seed`), every
+                         decision logged for neig_policy_log                              */
+    int seed;      /* seed of the exploration generator                                  */
+    int reserved[4];
 } neig_params;
 
 /* Counters and timings of the most recent neig_schur call. */
@@ -69,6 +76,8 @@ typedef struct neig_stats {
        cycles of its three phases (window QR; spike test and swaps; re-Hessenberg) */
     double aed_qr_iters, aed_swaps, aed_cyc_qr, aed_cyc_defl, aed_cyc_hess;
     double aed_late;     /* deflations found above a block that failed the spike test */
+    double policy_used, policy_fallback;  /* proposals taken from the network / the default rules */
+    double aed_flops;    /* algorithmic flops of the AED windows alone: 10 nw^3 per AED launch */
 } neig_stats;
 
 /*
@@ -91,16 +100,59 @@ typedef struct neig_stats {
  */
 int neig_schur(int n, double *H, int ldh, double *Z, int ldz, double *wr, double *wi, hipStream_t stream);
 
+/* Largest batch one neig_schur_batched call takes. */
+#define NEIG_BATCH_MAX 65536
+
 /*
  * neig_schur_batched -- neig_schur on `batch` independent problems of uneven
- * order in one call.
- *   n, ldh, ldz  host arrays [batch].
- *   H, Z, wr, wi device arrays [batch] of device pointers (one per problem).
- *   info         device int[batch]: per-problem return value as for neig_schur.
- * Returns 0 or a negative argument / HIP error code for the call as a whole.
+ * order in one persistent launch (the method of Section 3.2 run per problem by
+ * one workgroup that keeps its window factors in LDS; problems are taken from a
+ * device work queue, largest first).
+ *   batch        0 <= batch <= NEIG_BATCH_MAX.
+ *   n, ldh, ldz  device int arrays [batch]: order and leading dimensions.
+ *   H, Z, wr, wi device arrays [batch] of device pointers, one per problem, with
+ *                the meaning, layout and results of neig_schur's arguments.
+ *   info         device int[batch]: per-problem result as neig_schur returns it
+ *                (0; -2 also for NaN/Inf in H; -2..-8 for an invalid n, H, ldh,
+ *                Z, ldz, wr or wi entry of that problem, which is then left
+ *                untouched; > 0 unconverged leading rows).
+ *   stream       the work is ordered on this stream; the call returns after
+ *                enqueueing it (asynchronous: results are ready once the
+ *                stream reaches that point).
+ * Every array is read on the device when the work runs, so the call can be
+ * captured in a HIP graph and replayed with new contents in the same arrays.
+ * All batched calls on a device share one fixed-size library descriptor table:
+ * calls (and graph replays) must not overlap in time, e.g. keep them on one
+ * stream.  Per-size-class tuning comes from neig_set_batched_tune; the
+ * deflation criterion, nibble and exceptional-shift settings from neig_params.
+ * Returns 0 or a negative code for the call as a whole (-1 batch out of range).
  */
 int neig_schur_batched(int batch, const int *n, double *const *H, const int *ldh, double *const *Z, const int *ldz,
                        double *const *wr, double *const *wi, int *info, hipStream_t stream);
+
+/* Size classes of the batched solver. */
+#define NEIG_BATCH_CLASSES 6
+
+/*
+ * neig_set_batched_tune -- per-size-class control parameters of
+ * neig_schur_batched (Section 3.2: AED window, shifts per sweep, the size below
+ * which a block is solved by the in-LDS double-shift QR, and the chase window).
+ * A problem of order m uses the first class k with m <= n_hi[k]; the last class
+ * takes every larger m (its n_hi is ignored).
+ *   nclass          1..NEIG_BATCH_CLASSES.
+ *   n_hi            host int[nclass], strictly increasing.
+ *   nw, ns, nmin,   host int[nclass]: 2 <= nw, nmin <= 96; ns even, 2..32;
+ *   chase_w         3*(ns/2)+2 <= chase_w <= 96.
+ * Returns 0 or -k for the first invalid argument k; the table is unchanged on error.
+ */
+int neig_set_batched_tune(int nclass, const int *n_hi, const int *nw, const int *ns, const int *nmin,
+                          const int *chase_w);
+
+/*
+ * neig_get_batched_tune -- the current per-size-class table.  *nclass receives
+ * NEIG_BATCH_CLASSES; the other host arrays need that many entries.
+ */
+int neig_get_batched_tune(int *nclass, int *n_hi, int *nw, int *ns, int *nmin, int *chase_w);
 
 /*
  * neig_sweep -- one multishift QR sweep (Section 3.2, "Bulge chasing step"):
@@ -154,6 +206,89 @@ void neig_finalize(void);
 
 /* Version / build string. */
 const char *neig_version(void);
+
+/*
+ * Parameter-proposal network (not part of the paper's method: an addition that
+ * chooses the method's two tunables of Section 3.2, the number of shifts of the
+ * next sweep and the size of the next deflation window, per iteration).  A
+ * 24-64-64-(8+8) perceptron with ReLU hidden layers; the two 8-way heads score
+ * the bins neig_policy_bins reports.  Parameters are NEIG_MLP_NPARAM floats laid
+ * out as mu[24], sd[24] (fixed input normalisation), W1[64][24], b1[64],
+ * W2[64][64], b2[64], W3[16][64], b3[16] (row-major); the input is
+ * (x - mu) / sd.
+ *
+ * Features of one decision (active block [ktop, kbot] of order m, after a
+ * deflation window): f0 = log m; f1..f19 = the 5%, 10%, ..., 95% quantiles
+ * (linear interpolation between order statistics) of log(|h(k,k-1)| /
+ * (||H||_F / sqrt n)) over at most 1024 subdiagonal entries
+ * k = ktop+1+floor(i (m-1) / S), i < S = min(m-1, 1024); f20 = log(1e-30 + mean
+ * |ritz| / (||H||_F / sqrt n)), f21 = std |ritz| / mean |ritz|, f22 = share of
+ * non-real Ritz values, over the undeflated Ritz values of the last window (all
+ * three 0 when there are none); f23 = deflations of the last window / its size.
+ */
+#define NEIG_MLP_NPARAM 6848
+
+/* Bins of the two heads: ns_bins[8] shift counts, nw_bins[8] window sizes (host out). */
+int neig_policy_bins(int *ns_bins, int *nw_bins);
+
+/*
+ * neig_policy_set -- install the network used by params.policy = 1 (host array
+ * of NEIG_MLP_NPARAM floats, copied), or remove it (theta NULL).  A proposal is
+ * used only when the softmax probability of the chosen bin is at least min_conf
+ * on both heads; otherwise the default rules decide.  Returns 0, -1 (nparam),
+ * -3 (min_conf not in [0, 1]).
+ */
+int neig_policy_set(const float *theta, int nparam, float min_conf);
+
+/*
+ * neig_policy_log -- the decisions of the most recent neig_schur call with
+ * policy 1 or 2.  For decision i < min(count, cap): feat[24 i ..] its features,
+ * bins[2 i ..] the (shift, window) bins applied (or proposed, when the default
+ * rules decided), stats[4 i ..] = deflations of the next window, milliseconds
+ * from the decision to the end of that window, the order m of the active
+ * block, and 1 if the bins were applied.  Host arrays.  Returns count (>= 0).
+ */
+int neig_policy_log(int cap, float *feat, int *bins, float *stats);
+
+/*
+ * neig_policy_features -- the features of the active block [ktop, kbot] of H
+ * (device, order n, leading dimension ldh) as the solver computes them, with
+ * hnorm = ||H||_F and extra[4] (host) = f20..f23, and the installed network's
+ * bins and probabilities for them (all host out: feat[24], bins[2], conf[2]).
+ * Synchronous.  Returns 0 or -k for invalid argument k.
+ */
+int neig_policy_features(int n, const double *H, int ldh, int ktop, int kbot, double hnorm, const float *extra,
+                         float *feat, int *bins, float *conf, hipStream_t stream);
+
+/*
+ * neig_mlp_grad -- loss and gradient of the reward-weighted cross-entropy
+ *   L = (1/B) sum_i w_i (-log softmax(z_i[0:8])[a_i] - log softmax(z_i[8:16])[c_i])
+ * of a mini-batch, z_i the network's scores of X[i] (FP32 arithmetic).
+ *   batch   B >= 1.
+ *   X       device float[B][24]; a, c device int[B] in [0, 8); w device float[B].
+ *   theta   device float[NEIG_MLP_NPARAM].
+ *   grad    device float[NEIG_MLP_NPARAM] out (zero for mu and sd); loss device float out.
+ * Asynchronous on `stream`.  Returns 0, -1 (batch), or a HIP error code.
+ */
+int neig_mlp_grad(int batch, const float *X, const int *a, const int *c, const float *w, const float *theta,
+                  float *grad, float *loss, hipStream_t stream);
+
+/*
+ * neig_mlp_adam -- one Adam step (Kingma & Ba, bias-corrected) on the trainable
+ * entries of theta (device), with moments m, v (device, NEIG_MLP_NPARAM floats,
+ * zero before the first step); step >= 1 counts the steps.  Returns 0, -5 (step).
+ */
+int neig_mlp_adam(float *theta, const float *grad, float *m, float *v, int step, float lr, hipStream_t stream);
+
+/*
+ * neig_mlp_infer -- the network's scores with BF16 operands and FP32 sums:
+ * weights and each layer's input rounded to BF16 (nearest even), biases FP32.
+ *   X device float[B][24]; logits device float[B][16] out; bins device int[B][2]
+ *   out (best shift bin, best window bin); conf device float[B][2] out (their
+ *   softmax probabilities).  Asynchronous.  Returns 0, -1 (batch).
+ */
+int neig_mlp_infer(int batch, const float *X, const float *theta, float *logits, int *bins, float *conf,
+                   hipStream_t stream);
 
 #ifdef __cplusplus
 }

@@ -13,6 +13,10 @@ from .binding import (  # noqa: F401
     load_library,
     schur,
     schur_batched,
+    batched_tables,
+    launch_batched,
+    set_batched_tune,
+    get_batched_tune,
     set_params,
     get_params,
     get_stats,
@@ -20,4 +24,11 @@ from .binding import (  # noqa: F401
     aed,
     small_schur,
     finalize,
+    policy_bins,
+    policy_set,
+    policy_log,
+    policy_features,
+    mlp_grad,
+    mlp_adam,
+    mlp_infer,
 )

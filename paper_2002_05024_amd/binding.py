@@ -39,7 +39,9 @@ class Params(ctypes.Structure):
         ("nibble", _i),
         ("exc", _i),
         ("timing", _i),
-        ("reserved", _i * 6),
+        ("policy", _i),
+        ("seed", _i),
+        ("reserved", _i * 4),
     ]
 
 
@@ -74,6 +76,9 @@ class Stats(ctypes.Structure):
         ("aed_cyc_defl", ctypes.c_double),
         ("aed_cyc_hess", ctypes.c_double),
         ("aed_late", ctypes.c_double),
+        ("policy_used", ctypes.c_double),
+        ("policy_fallback", ctypes.c_double),
+        ("aed_flops", ctypes.c_double),
     ]
 
 
@@ -93,8 +98,26 @@ def load_library():
     lib = ctypes.CDLL(_LIB_PATH)
     lib.neig_schur.argtypes = [_i, _vp, _i, _vp, _i, _vp, _vp, _vp]
     lib.neig_schur.restype = _i
-    lib.neig_schur_batched.argtypes = [_i, _ip, _vp, _ip, _vp, _ip, _vp, _vp, _vp, _vp]
+    lib.neig_schur_batched.argtypes = [_i, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp]
     lib.neig_schur_batched.restype = _i
+    _fp = ctypes.POINTER(ctypes.c_float)
+    sigs = {
+        "neig_policy_bins": [_ip, _ip],
+        "neig_policy_set": [_fp, _i, ctypes.c_float],
+        "neig_policy_log": [_i, _fp, _ip, _fp],
+        "neig_policy_features": [_i, _vp, _i, _i, _i, ctypes.c_double, _fp, _fp, _ip, _fp, _vp],
+        "neig_mlp_grad": [_i, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp],
+        "neig_mlp_adam": [_vp, _vp, _vp, _vp, _i, ctypes.c_float, _vp],
+        "neig_mlp_infer": [_i, _vp, _vp, _vp, _vp, _vp, _vp],
+    }
+    for name, args in sigs.items():
+        fn = getattr(lib, name)
+        fn.argtypes = args
+        fn.restype = _i
+    lib.neig_set_batched_tune.argtypes = [_i, _ip, _ip, _ip, _ip, _ip]
+    lib.neig_set_batched_tune.restype = _i
+    lib.neig_get_batched_tune.argtypes = [_ip, _ip, _ip, _ip, _ip, _ip]
+    lib.neig_get_batched_tune.restype = _i
     lib.neig_sweep.argtypes = [_i, _vp, _i, _vp, _i, _i, _i, _i, _dp, _dp, _vp]
     lib.neig_sweep.restype = _i
     lib.neig_aed.argtypes = [_i, _vp, _i, _vp, _i, _i, _i, _i, _ip, _ip, _dp, _dp, _vp]
@@ -239,33 +262,183 @@ def aed(H, Z, ktop, kbot, nw, stream=None):
     return nd.value, sr[:k].copy(), si[:k].copy()
 
 
-def schur_batched(Hs, Zs=None, stream=None):
-    """Real Schur forms of a list of independent problems of uneven size in one
-    asynchronous call.  Returns (wr list, wi list, Z list, info tensor)."""
-    torch = _torch()
-    import numpy as np
+class BatchedCall:
+    """Device-side argument tables of one neig_schur_batched call.  Keeping this
+    object alive keeps the tables alive, which a captured graph needs."""
 
-    lib = load_library()
+    def __init__(self, Hs, Zs, wrs, wis, info, meta, ptrs):
+        self.Hs, self.Zs, self.wrs, self.wis, self.info = Hs, Zs, wrs, wis, info
+        self.meta, self.ptrs = meta, ptrs
+
+
+def batched_tables(Hs, Zs=None):
+    """Output buffers and the device argument tables for a list of problems."""
+    torch = _torch()
     b = len(Hs)
     dev = Hs[0].device if b else torch.device("cuda")
     if Zs is None:
         Zs = [torch.eye(h.shape[0], dtype=torch.float64, device=dev).t().contiguous().t() for h in Hs]
-    ns = np.array([h.shape[0] for h in Hs], dtype=np.int32)
-    ldh = np.array([_check_matrix("H", h, int(k)) for h, k in zip(Hs, ns)], dtype=np.int32)
-    ldz = np.array([_check_matrix("Z", z, int(k)) for z, k in zip(Zs, ns)], dtype=np.int32)
-    wrs = [torch.empty(int(k), dtype=torch.float64, device=dev) for k in ns]
-    wis = [torch.empty(int(k), dtype=torch.float64, device=dev) for k in ns]
+    if len(Zs) != b:
+        raise NeigError("schur_batched: Hs and Zs differ in length")
+    ns = [int(h.shape[0]) for h in Hs]
+    ldh = [_check_matrix("H", h, k) for h, k in zip(Hs, ns)]
+    ldz = [_check_matrix("Z", z, k) for z, k in zip(Zs, ns)]
+    wrs = [torch.empty(k, dtype=torch.float64, device=dev) for k in ns]
+    wis = [torch.empty(k, dtype=torch.float64, device=dev) for k in ns]
+    meta = torch.tensor(ns + ldh + ldz, dtype=torch.int32, device=dev)
     ptrs = torch.tensor([h.data_ptr() for h in Hs] + [z.data_ptr() for z in Zs]
                         + [w.data_ptr() for w in wrs] + [w.data_ptr() for w in wis],
                         dtype=torch.int64, device=dev)
     info = torch.zeros(b, dtype=torch.int32, device=dev)
-    base = ptrs.data_ptr()
-    rc = lib.neig_schur_batched(b, ns.ctypes.data_as(_ip), ctypes.c_void_p(base), ldh.ctypes.data_as(_ip),
-                                ctypes.c_void_p(base + 8 * b), ldz.ctypes.data_as(_ip),
-                                ctypes.c_void_p(base + 16 * b), ctypes.c_void_p(base + 24 * b),
-                                ctypes.c_void_p(info.data_ptr()), _stream_ptr(stream))
+    return BatchedCall(Hs, Zs, wrs, wis, info, meta, ptrs)
+
+
+def launch_batched(call, stream=None) -> None:
+    """Enqueue neig_schur_batched for the tables of ``call`` (asynchronous)."""
+    lib = load_library()
+    b = len(call.Hs)
+    m, p = call.meta.data_ptr(), call.ptrs.data_ptr()
+    vp = ctypes.c_void_p
+    rc = lib.neig_schur_batched(b, vp(m), vp(p), vp(m + 4 * b), vp(p + 8 * b), vp(m + 8 * b), vp(p + 16 * b),
+                                vp(p + 24 * b), vp(call.info.data_ptr()), _stream_ptr(stream))
     _raise("neig_schur_batched", rc)
-    return wrs, wis, Zs, info, ptrs
+
+
+def schur_batched(Hs, Zs=None, stream=None):
+    """Real Schur forms of a list of independent problems of uneven size in one
+    asynchronous call on ``stream`` (default: torch's current stream).  Returns a
+    :class:`BatchedCall` holding Hs (overwritten by S), Zs, wrs, wis and the
+    per-problem info tensor."""
+    call = batched_tables(Hs, Zs)
+    launch_batched(call, stream)
+    return call
+
+
+def set_batched_tune(n_hi, nw, ns, nmin, chase_w) -> None:
+    """Per-size-class parameters of the batched solver (lists of equal length)."""
+    lib = load_library()
+    k = len(nw)
+    arrs = [(ctypes.c_int * k)(*[int(x) for x in a]) for a in (list(n_hi) + [0] * (k - len(n_hi)), nw, ns, nmin,
+                                                                chase_w)]
+    rc = lib.neig_set_batched_tune(k, *arrs)
+    if rc != 0:
+        raise NeigError(f"neig_set_batched_tune: invalid argument {-rc}")
+
+
+def get_batched_tune() -> dict:
+    lib = load_library()
+    k = 16
+    cnt = ctypes.c_int()
+    arrs = [(ctypes.c_int * k)() for _ in range(5)]
+    lib.neig_get_batched_tune(ctypes.byref(cnt), *arrs)
+    names = ("n_hi", "nw", "ns", "nmin", "chase_w")
+    return {nm: list(a)[: cnt.value] for nm, a in zip(names, arrs)}
+
+
+MLP_NPARAM = 6848
+MLP_NIN = 24
+
+
+def policy_bins():
+    """(shift-count bins, window-size bins) of the proposal network's heads."""
+    lib = load_library()
+    a, b = (ctypes.c_int * 8)(), (ctypes.c_int * 8)()
+    lib.neig_policy_bins(a, b)
+    return list(a), list(b)
+
+
+def policy_set(theta=None, min_conf: float = 0.0) -> None:
+    """Install (host array of MLP_NPARAM floats) or remove (None) the network."""
+    import numpy as np
+
+    lib = load_library()
+    if theta is None:
+        rc = lib.neig_policy_set(None, 0, float(min_conf))
+    else:
+        th = np.ascontiguousarray(theta, dtype=np.float32)
+        rc = lib.neig_policy_set(th.ctypes.data_as(ctypes.POINTER(ctypes.c_float)), int(th.size), float(min_conf))
+    if rc != 0:
+        raise NeigError(f"neig_policy_set: invalid argument {-rc}")
+
+
+def policy_log():
+    """Decisions of the last neig_schur call: (features [k,24], bins [k,2],
+    stats [k,4] = deflations, ms, m, applied)."""
+    import numpy as np
+
+    lib = load_library()
+    k = lib.neig_policy_log(0, None, None, None)
+    feat = np.zeros((max(k, 1), MLP_NIN), dtype=np.float32)
+    bins = np.zeros((max(k, 1), 2), dtype=np.int32)
+    st = np.zeros((max(k, 1), 4), dtype=np.float32)
+    fp = ctypes.POINTER(ctypes.c_float)
+    lib.neig_policy_log(k, feat.ctypes.data_as(fp), bins.ctypes.data_as(_ip), st.ctypes.data_as(fp))
+    return feat[:k], bins[:k], st[:k]
+
+
+def policy_features(H, ktop: int, kbot: int, hnorm: float, extra, stream=None):
+    """Features of the active block [ktop, kbot] of the device matrix H and the
+    installed network's (bins, probabilities) for them."""
+    import numpy as np
+
+    lib = load_library()
+    n = int(H.shape[0])
+    ldh = _check_matrix("H", H, n)
+    ex = np.ascontiguousarray(extra, dtype=np.float32)
+    feat = np.zeros(MLP_NIN, dtype=np.float32)
+    bins = np.zeros(2, dtype=np.int32)
+    conf = np.zeros(2, dtype=np.float32)
+    fp = ctypes.POINTER(ctypes.c_float)
+    rc = lib.neig_policy_features(n, ctypes.c_void_p(H.data_ptr()), ldh, int(ktop), int(kbot), float(hnorm),
+                                  ex.ctypes.data_as(fp), feat.ctypes.data_as(fp), bins.ctypes.data_as(_ip),
+                                  conf.ctypes.data_as(fp), _stream_ptr(stream))
+    _raise("neig_policy_features", rc)
+    return feat, bins, conf
+
+
+def _dev(t, dtype, name):
+    torch = _torch()
+    if not (isinstance(t, torch.Tensor) and t.is_cuda and t.dtype == dtype and t.is_contiguous()):
+        raise NeigError(f"{name}: expected a contiguous {dtype} GPU tensor")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def mlp_grad(X, a, c, w, theta, stream=None):
+    """(loss, grad) of the reward-weighted cross-entropy on the GPU (FP32)."""
+    torch = _torch()
+    lib = load_library()
+    grad = torch.empty(MLP_NPARAM, dtype=torch.float32, device=X.device)
+    loss = torch.empty(1, dtype=torch.float32, device=X.device)
+    rc = lib.neig_mlp_grad(int(X.shape[0]), _dev(X, torch.float32, "X"), _dev(a, torch.int32, "a"),
+                           _dev(c, torch.int32, "c"), _dev(w, torch.float32, "w"),
+                           _dev(theta, torch.float32, "theta"), ctypes.c_void_p(grad.data_ptr()),
+                           ctypes.c_void_p(loss.data_ptr()), _stream_ptr(stream))
+    _raise("neig_mlp_grad", rc)
+    return loss, grad
+
+
+def mlp_adam(theta, grad, m, v, step: int, lr: float, stream=None) -> None:
+    torch = _torch()
+    lib = load_library()
+    rc = lib.neig_mlp_adam(_dev(theta, torch.float32, "theta"), _dev(grad, torch.float32, "grad"),
+                           _dev(m, torch.float32, "m"), _dev(v, torch.float32, "v"), int(step), float(lr),
+                           _stream_ptr(stream))
+    _raise("neig_mlp_adam", rc)
+
+
+def mlp_infer(X, theta, stream=None):
+    """(logits [B,16], bins [B,2], conf [B,2]) with BF16 operands on the GPU."""
+    torch = _torch()
+    lib = load_library()
+    B = int(X.shape[0])
+    logits = torch.empty((B, 16), dtype=torch.float32, device=X.device)
+    bins = torch.empty((B, 2), dtype=torch.int32, device=X.device)
+    conf = torch.empty((B, 2), dtype=torch.float32, device=X.device)
+    rc = lib.neig_mlp_infer(B, _dev(X, torch.float32, "X"), _dev(theta, torch.float32, "theta"),
+                            ctypes.c_void_p(logits.data_ptr()), ctypes.c_void_p(bins.data_ptr()),
+                            ctypes.c_void_p(conf.data_ptr()), _stream_ptr(stream))
+    _raise("neig_mlp_infer", rc)
+    return logits, bins, conf
 
 
 def set_params(**kw) -> None:

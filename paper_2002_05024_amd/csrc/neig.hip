@@ -14,6 +14,8 @@
 #include "chase.hip"
 #include "gemm.hip"
 #include "util.hip"
+#include "batched.hip"
+#include "mlp.hip"
 
 #include <algorithm>
 #include <chrono>
@@ -34,8 +36,37 @@ inline void ck(hipError_t e) {
 }
 
 neig_params g_params = {};
+
+// Per-size-bucket settings of the batched solver (problems with n <= hi use the
+// bucket); the autotuner replaces these through neig_set_batched_tune.
+struct BatchTable {
+    int hi[B_NBUCKET];
+    BTune t[B_NBUCKET];
+};
+BatchTable g_btab = {{96, 256, 512, 768, 1024, 1 << 30},
+                     {{48, 16, 96, 96}, {48, 16, 96, 96}, {64, 32, 96, 96}, {64, 32, 96, 96}, {64, 32, 96, 96},
+                      {64, 32, 96, 96}}};
 neig_stats g_stats = {};
 std::mutex g_mutex;
+
+// Parameter-proposal network: bins of the two proposals, the weights (host copy,
+// uploaded to each device on first use after a change), the confidence below
+// which the default heuristics are used, and the log of the last run.
+const int kNsBins[MLP_NBIN] = {4, 8, 12, 16, 20, 24, 28, 32};
+const int kNwBins[MLP_NBIN] = {24, 32, 40, 48, 56, 64, 80, 96};
+struct PolicyState {
+    std::vector<float> theta;  // empty: no network installed
+    long long version = 0;
+    float min_conf = 0.0f;
+};
+PolicyState g_policy;
+struct PolicySample {
+    float feat[MLP_NIN];
+    int bins[2];
+    float nd, ms, m;
+    int used_net;
+};
+std::vector<PolicySample> g_policy_log;
 
 constexpr int kMaxDevices = 64;
 constexpr int kStatusInts = 64;
@@ -76,9 +107,31 @@ struct DeviceWs {
     double *h_poly = nullptr; size_t h_poly_cap = 0;
     int *h_flag = nullptr; size_t h_flag_cap = 0;
     std::vector<hipEvent_t> events;               // pool for timing mode
+    int cus = 0;                                  // compute units (persistent grid size)
+    // batched path: problem descriptors, processing order, work counter; fixed
+    // capacity, allocated once, so a captured batched launch never refers to
+    // memory that a later call frees
+    BProb *bprob = nullptr;
+    int *border = nullptr;
+    int *bnext = nullptr;
+    // network: weights, per-decision output (24 features, 2 bins, 2 probabilities),
+    // training partials
+    float *theta = nullptr;
+    long long theta_version = -1;
+    float *pol_out = nullptr;
+    float *h_pol_out = nullptr;
+    float *mlp_part = nullptr; size_t mlp_part_cap = 0;
 };
 
 DeviceWs g_ws[kMaxDevices];
+
+// Let a kernel take all the LDS its static arrays leave free as dynamic LDS.
+void allow_dynamic_lds(const void *fn, size_t lds_max) {
+    hipFuncAttributes at;
+    if (hipFuncGetAttributes(&at, fn) == hipSuccess && at.sharedSizeBytes < lds_max)
+        (void)hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)(lds_max - at.sharedSizeBytes));
+    (void)hipGetLastError();
+}
 
 DeviceWs &workspace() {
     int dev = 0;
@@ -94,12 +147,17 @@ DeviceWs &workspace() {
     int c = NEIG_CHASE_MAX;
     while (c > 8 && (size_t)(2 * (c + 1) * (c + 2)) * 8 + 2048 > w.lds_max) --c;
     w.chase_max = c;
-    (void)hipFuncSetAttribute((const void *)k_small_qr, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
-    (void)hipFuncSetAttribute((const void *)k_aed, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
-    (void)hipFuncSetAttribute((const void *)k_chase, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
-    (void)hipFuncSetAttribute((const void *)k_update, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
-    (void)hipGetLastError();
+    for (const void *fn : {(const void *)k_small_qr, (const void *)k_aed, (const void *)k_chase,
+                           (const void *)k_update, (const void *)k_batched})
+        allow_dynamic_lds(fn, w.lds_max);
+    ck(hipDeviceGetAttribute(&w.cus, hipDeviceAttributeMultiprocessorCount, dev));
     ck(hipMalloc((void **)&w.ist, kStatusInts * sizeof(int)));
+    ck(hipMalloc((void **)&w.bprob, (size_t)NEIG_BATCH_MAX * sizeof(BProb)));
+    ck(hipMalloc((void **)&w.border, (size_t)NEIG_BATCH_MAX * sizeof(int)));
+    ck(hipMalloc((void **)&w.bnext, sizeof(int)));
+    ck(hipMalloc((void **)&w.theta, (size_t)MLP_NPARAM * sizeof(float)));
+    ck(hipMalloc((void **)&w.pol_out, 32 * sizeof(float)));
+    ck(hipHostMalloc((void **)&w.h_pol_out, 32 * sizeof(float), hipHostMallocDefault));
     grow_host(&w.h_ist, &w.h_ist_cap, (size_t)kStatusInts);
     w.ready = true;
     return w;
@@ -108,9 +166,10 @@ DeviceWs &workspace() {
 void free_workspace(DeviceWs &w) {
     if (!w.ready) return;
     for (void *p : {(void *)w.ut, (void *)w.vt, (void *)w.poly, (void *)w.dbuf, (void *)w.rot, (void *)w.ist,
-                    (void *)w.flag})
+                    (void *)w.flag, (void *)w.bprob, (void *)w.border, (void *)w.bnext,
+                    (void *)w.theta, (void *)w.pol_out, (void *)w.mlp_part})
         if (p) (void)hipFree(p);
-    for (void *p : {(void *)w.h_ist, (void *)w.h_dbuf, (void *)w.h_poly, (void *)w.h_flag})
+    for (void *p : {(void *)w.h_ist, (void *)w.h_dbuf, (void *)w.h_poly, (void *)w.h_flag, (void *)w.h_pol_out})
         if (p) (void)hipHostFree(p);
     for (hipEvent_t e : w.events) (void)hipEventDestroy(e);
     w = DeviceWs();
@@ -348,6 +407,7 @@ class Solver {
         stats_.aeds++;
         stats_.aed_deflated += nd;
         stats_.small_flops += 10.0 * nw * (double)nw * nw;
+        stats_.aed_flops += 10.0 * nw * (double)nw * nw;
         stats_.alg_flops += 10.0 * nw * (double)nw * nw;
         if (applied) stats_.alg_flops += 2.0 * nw * (double)nw * (kwtop + (n_ - kbot - 1) + n_);
         stats_.t_aed_ms += now_ms() - t0;
@@ -526,6 +586,72 @@ class Solver {
     }
 
     // ---- whole solve -----------------------------------------------------
+    // ---- parameter proposals ----------------------------------------------
+    // The features of the active block [ktop, kbot] and the network's bins, by
+    // one k_policy launch and one read-back.  The last four features come from
+    // the host: Ritz-value statistics of the previous deflation window and the
+    // share of it that deflated.
+    struct Decision {
+        float feat[MLP_NIN];
+        int bins[2];
+        float conf[2];
+    };
+
+    void upload_policy() {
+        if (ws_.theta_version == g_policy.version) return;
+        std::vector<float> th = g_policy.theta;
+        if (th.empty()) {  // neutral weights: features are still computed
+            th.assign(MLP_NPARAM, 0.0f);
+            for (int k = 0; k < MLP_NIN; ++k) th[MLP_O_SD + k] = 1.0f;
+        }
+        ck(hipMemcpy(ws_.theta, th.data(), (size_t)MLP_NPARAM * sizeof(float), hipMemcpyHostToDevice));
+        ws_.theta_version = g_policy.version;
+    }
+
+    Decision propose(int ktop, int kbot, const std::vector<Eig> &ritz, int nd_prev, int nw_prev) {
+        upload_policy();
+        const double scale = hnorm_ > 0.0 ? hnorm_ / std::sqrt((double)n_) : 1.0;
+        float f20 = 0.0f, f21 = 0.0f, f22 = 0.0f;
+        if (!ritz.empty()) {
+            double sum = 0.0, sq = 0.0, cplx = 0.0;
+            for (const Eig &e : ritz) {
+                const double r = std::hypot(e.re, e.im);
+                sum += r;
+                sq += r * r;
+                cplx += (e.im != 0.0) ? 1.0 : 0.0;
+            }
+            const double k = (double)ritz.size(), mean = sum / k;
+            const double var = std::max(0.0, sq / k - mean * mean);
+            f20 = (float)std::log(1e-30 + mean / scale);
+            f21 = (float)(std::sqrt(var) / (mean + 1e-300));
+            f22 = (float)(cplx / k);
+        }
+        const float f23 = nw_prev > 0 ? (float)nd_prev / (float)nw_prev : 0.0f;
+        float *out = ws_.pol_out;
+        timed(kOther, [&] {
+            hipLaunchKernelGGL(k_policy, dim3(1), dim3(256), 0, st_, H_, ldh_, n_, ktop, kbot, hnorm_, f20, f21, f22,
+                               f23, ws_.theta, out, (int *)(out + MLP_NIN), out + MLP_NIN + 2);
+            ck(hipGetLastError());
+        });
+        ck(hipMemcpyAsync(ws_.h_pol_out, out, (MLP_NIN + 4) * sizeof(float), hipMemcpyDeviceToHost, st_));
+        sync_collect();
+        Decision d;
+        std::memcpy(d.feat, ws_.h_pol_out, MLP_NIN * sizeof(float));
+        std::memcpy(d.bins, ws_.h_pol_out + MLP_NIN, 2 * sizeof(int));
+        std::memcpy(d.conf, ws_.h_pol_out + MLP_NIN + 2, 2 * sizeof(float));
+        return d;
+    }
+
+    // counter-based generator for exploration (splitmix64 of seed and counter)
+    uint64_t rng_state_ = 0;
+    int explore_bin() {
+        uint64_t z = (rng_state_ += 0x9e3779b97f4a7c15ull);
+        z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ull;
+        z = (z ^ (z >> 27)) * 0x94d049bb133111ebull;
+        z ^= z >> 31;
+        return (int)(z % MLP_NBIN);
+    }
+
     int run() {
         double t0 = now_ms();
         if (!prep()) return -2;
@@ -533,6 +659,13 @@ class Solver {
         int total = 0, ndefl = 0;
         std::vector<Eig> ritz;
         int info = 0;
+        const int mode = p_.policy;
+        rng_state_ = 0x243f6a8885a308d3ull ^ (uint64_t)(unsigned)p_.seed;
+        policy_log_.clear();
+        int nw_next = 0, ns_next = 0;
+        PolicySample pending;
+        bool have_pending = false;
+        double t_decide = 0.0;
         while (kbot >= 0) {
             const int ktop = scan(kbot);
             const int m = kbot - ktop + 1;
@@ -544,6 +677,8 @@ class Solver {
                 }
                 kbot = ktop - 1;
                 ndefl = 0;
+                have_pending = false;
+                nw_next = ns_next = 0;
                 continue;
             }
             if (++total > maxit_) {
@@ -551,14 +686,52 @@ class Solver {
                 break;
             }
             stats_.iterations++;
-            const int nw = default_nw(m);
+            const int nw = nw_next > 0 ? std::min(nw_next, m) : default_nw(m);
             const int nd = aed(ktop, kbot, nw, ritz);
+            if (have_pending) {  // reward of the last proposal: this window's deflations per ms
+                pending.nd = (float)nd;
+                pending.ms = (float)(now_ms() - t_decide);
+                policy_log_.push_back(pending);
+                have_pending = false;
+            }
+            nw_next = ns_next = 0;
             kbot -= nd;
             ndefl = (nd > 0) ? 0 : ndefl + 1;
             const int m2 = kbot - ktop + 1;
             if (m2 <= nmin_) continue;
+            if (mode != 0) {
+                t_decide = now_ms();
+                Decision d = propose(ktop, kbot, ritz, nd, nw);
+                int bns = d.bins[0], bnw = d.bins[1];
+                int used = 0;
+                if (mode == 2) {
+                    bns = explore_bin();
+                    bnw = explore_bin();
+                    used = 1;
+                } else if (!g_policy.theta.empty() && d.conf[0] >= g_policy.min_conf &&
+                           d.conf[1] >= g_policy.min_conf) {
+                    used = 1;
+                }
+                if (used) {
+                    ns_next = kNsBins[bns];
+                    nw_next = kNwBins[bnw];
+                    stats_.policy_used++;
+                } else {
+                    stats_.policy_fallback++;
+                }
+                std::memcpy(pending.feat, d.feat, sizeof(pending.feat));
+                pending.bins[0] = bns;
+                pending.bins[1] = bnw;
+                pending.m = (float)m2;
+                pending.used_net = used;
+                have_pending = true;
+            }
             if (nd > 0 && 100 * nd > nibble_ * nw) continue;
-            const int ns = default_ns(m2);
+            int ns = default_ns(m2);
+            if (ns_next > 0) {
+                ns = std::min(ns_next, std::max(2, m2 / 3));
+                ns = std::max(2, ns - ns % 2);
+            }
             std::vector<Eig> sh;
             if (ndefl > 0 && ndefl % exc_ == 0) {
                 const int lo = std::max(ktop, kbot - ns - 1);
@@ -592,6 +765,8 @@ class Solver {
         stats_.t_total_ms = now_ms() - t0;
         return info;
     }
+
+    std::vector<PolicySample> policy_log_;
 
     // Standardise any 2x2 block not yet in standard form, then read off (wr, wi).
     void finish_std() {
@@ -663,6 +838,7 @@ extern "C" int neig_schur(int n, double *H, int ldh, double *Z, int ldz, double 
     try {
         Solver s(n, H, ldh, Z, ldz, stream);
         int info = s.run();
+        g_policy_log.swap(s.policy_log_);
         if (info == -2) return -2;
         s.eigenvalues(wr, wi);
         s.sync();
@@ -757,7 +933,7 @@ extern "C" int neig_aed(int n, double *H, int ldh, double *Z, int ldz, int ktop,
 extern "C" int neig_schur_batched(int batch, const int *n, double *const *H, const int *ldh, double *const *Z,
                                   const int *ldz, double *const *wr, double *const *wi, int *info,
                                   hipStream_t stream) {
-    if (batch < 0) return -1;
+    if (batch < 0 || batch > NEIG_BATCH_MAX) return -1;
     if (batch == 0) return 0;
     if (!n) return -2;
     if (!H) return -3;
@@ -767,22 +943,220 @@ extern "C" int neig_schur_batched(int batch, const int *n, double *const *H, con
     if (!wr) return -7;
     if (!wi) return -8;
     if (!info) return -9;
-    // device pointer tables -> host copies
-    std::vector<double *> hH(batch), hZ(batch), hwr(batch), hwi(batch);
+    std::lock_guard<std::mutex> lock(g_mutex);
     try {
-        ck(hipMemcpyAsync(hH.data(), H, batch * sizeof(double *), hipMemcpyDeviceToHost, stream));
-        ck(hipMemcpyAsync(hZ.data(), Z, batch * sizeof(double *), hipMemcpyDeviceToHost, stream));
-        ck(hipMemcpyAsync(hwr.data(), wr, batch * sizeof(double *), hipMemcpyDeviceToHost, stream));
-        ck(hipMemcpyAsync(hwi.data(), wi, batch * sizeof(double *), hipMemcpyDeviceToHost, stream));
-        ck(hipStreamSynchronize(stream));
-        std::vector<int> inf(batch, 0);
-        for (int b = 0; b < batch; ++b) inf[b] = neig_schur(n[b], hH[b], ldh[b], hZ[b], ldz[b], hwr[b], hwi[b], stream);
-        ck(hipMemcpyAsync(info, inf.data(), batch * sizeof(int), hipMemcpyHostToDevice, stream));
-        ck(hipStreamSynchronize(stream));
+        DeviceWs &ws = workspace();
+        hipLaunchKernelGGL(k_batched_pack, dim3((batch + 255) / 256), dim3(256), 0, stream, ws.bprob, ws.border,
+                           ws.bnext, info, n, ldh, ldz, H, Z, wr, wi, batch);
+        ck(hipGetLastError());
+        BArgs A;
+        std::memset(&A, 0, sizeof(A));
+        A.probs = ws.bprob;
+        A.order = ws.border;
+        A.nprob = batch;
+        A.next = ws.bnext;
+        A.info = info;
+        for (int k = 0; k < B_NBUCKET; ++k) {
+            A.bucket_hi[k] = g_btab.hi[k];
+            A.tune[k] = g_btab.t[k];
+            A.tune[k].nw = std::min(A.tune[k].nw, ws.small_max);
+            A.tune[k].nmin = std::min(A.tune[k].nmin, ws.small_max);
+            A.tune[k].wchase = std::min(A.tune[k].wchase, ws.chase_max);
+            A.tune[k].ns = std::min(A.tune[k].ns, 2 * B_MAX_BULGES);
+        }
+        A.criterion = g_params.deflation;
+        A.nibble = g_params.nibble > 0 ? g_params.nibble : 14;
+        A.exc = g_params.exc > 0 ? g_params.exc : 6;
+        A.maxit_factor = 30;
+        const int grid = std::max(1, std::min(batch, ws.cus > 0 ? ws.cus : 256));
+        const size_t lds = (size_t)(NEIG_CHASE_MAX + 1) * (NEIG_CHASE_MAX + 2) * sizeof(double) +
+                           (size_t)NEIG_CHASE_MAX * (NEIG_CHASE_MAX + 1) * sizeof(double);
+        hipLaunchKernelGGL(k_batched, dim3(grid), dim3(NT), lds, stream, A);
+        ck(hipGetLastError());
     } catch (const HipFail &f) {
         return -100 - (int)f.e;
     }
     return 0;
+}
+
+static_assert(B_NBUCKET == NEIG_BATCH_CLASSES, "size classes of the batched solver");
+
+extern "C" int neig_set_batched_tune(int nclass, const int *n_hi, const int *nw, const int *ns, const int *nmin,
+                                     const int *chase_w) {
+    if (nclass < 1 || nclass > B_NBUCKET) return -1;
+    if (!n_hi) return -2;
+    if (!nw) return -3;
+    if (!ns) return -4;
+    if (!nmin) return -5;
+    if (!chase_w) return -6;
+    for (int k = 0; k < nclass; ++k) {
+        if (k > 0 && k < nclass - 1 && n_hi[k] <= n_hi[k - 1]) return -2;
+        if (nw[k] < 2 || nw[k] > NEIG_SMALL_MAX) return -3;
+        if (ns[k] < 2 || ns[k] % 2 || ns[k] > 2 * B_MAX_BULGES) return -4;
+        if (nmin[k] < 2 || nmin[k] > NEIG_SMALL_MAX) return -5;
+        if (chase_w[k] < 3 * (ns[k] / 2) + 2 || chase_w[k] > NEIG_CHASE_MAX) return -6;
+    }
+    std::lock_guard<std::mutex> lock(g_mutex);
+    BatchTable t;
+    for (int k = 0; k < B_NBUCKET; ++k) {
+        const int src = std::min(k, nclass - 1);
+        t.hi[k] = k < nclass - 1 ? n_hi[k] : (1 << 30);
+        t.t[k] = {nw[src], ns[src], nmin[src], chase_w[src]};
+    }
+    g_btab = t;
+    return 0;
+}
+
+extern "C" int neig_get_batched_tune(int *nclass, int *n_hi, int *nw, int *ns, int *nmin, int *chase_w) {
+    if (!nclass) return -1;
+    if (!n_hi) return -2;
+    if (!nw) return -3;
+    if (!ns) return -4;
+    if (!nmin) return -5;
+    if (!chase_w) return -6;
+    std::lock_guard<std::mutex> lock(g_mutex);
+    *nclass = B_NBUCKET;
+    for (int k = 0; k < B_NBUCKET; ++k) {
+        n_hi[k] = g_btab.hi[k];
+        nw[k] = g_btab.t[k].nw;
+        ns[k] = g_btab.t[k].ns;
+        nmin[k] = g_btab.t[k].nmin;
+        chase_w[k] = g_btab.t[k].wchase;
+    }
+    return 0;
+}
+
+static_assert(MLP_NPARAM == NEIG_MLP_NPARAM, "network parameter count");
+
+extern "C" int neig_policy_bins(int *ns_bins, int *nw_bins) {
+    if (!ns_bins) return -1;
+    if (!nw_bins) return -2;
+    for (int k = 0; k < MLP_NBIN; ++k) {
+        ns_bins[k] = kNsBins[k];
+        nw_bins[k] = kNwBins[k];
+    }
+    return 0;
+}
+
+extern "C" int neig_policy_set(const float *theta, int nparam, float min_conf) {
+    if (theta && nparam != MLP_NPARAM) return -1;
+    if (!(min_conf >= 0.0f && min_conf <= 1.0f)) return -3;
+    std::lock_guard<std::mutex> lock(g_mutex);
+    if (theta) g_policy.theta.assign(theta, theta + MLP_NPARAM);
+    else g_policy.theta.clear();
+    g_policy.min_conf = min_conf;
+    g_policy.version++;
+    return 0;
+}
+
+extern "C" int neig_policy_log(int cap, float *feat, int *bins, float *stats) {
+    std::lock_guard<std::mutex> lock(g_mutex);
+    const int count = (int)g_policy_log.size();
+    const int k = std::min(std::max(cap, 0), count);
+    for (int i = 0; i < k; ++i) {
+        const PolicySample &q = g_policy_log[i];
+        if (feat) std::memcpy(feat + (size_t)MLP_NIN * i, q.feat, sizeof(q.feat));
+        if (bins) {
+            bins[2 * i] = q.bins[0];
+            bins[2 * i + 1] = q.bins[1];
+        }
+        if (stats) {
+            stats[4 * i] = q.nd;
+            stats[4 * i + 1] = q.ms;
+            stats[4 * i + 2] = q.m;
+            stats[4 * i + 3] = (float)q.used_net;
+        }
+    }
+    return count;
+}
+
+extern "C" int neig_policy_features(int n, const double *H, int ldh, int ktop, int kbot, double hnorm,
+                                    const float *extra, float *feat, int *bins, float *conf, hipStream_t stream) {
+    if (n < 1) return -1;
+    if (!H) return -2;
+    if (ldh < n) return -3;
+    if (ktop < 0 || ktop >= n) return -4;
+    if (kbot < ktop || kbot >= n) return -5;
+    if (!(hnorm >= 0.0)) return -6;
+    if (!extra) return -7;
+    if (!feat) return -8;
+    if (!bins) return -9;
+    if (!conf) return -10;
+    std::lock_guard<std::mutex> lock(g_mutex);
+    try {
+        DeviceWs &ws = workspace();
+        Solver s(n, const_cast<double *>(H), ldh, nullptr, n, stream);
+        s.upload_policy();
+        float *out = ws.pol_out;
+        hipLaunchKernelGGL(k_policy, dim3(1), dim3(256), 0, stream, H, ldh, n, ktop, kbot, hnorm, extra[0], extra[1],
+                           extra[2], extra[3], ws.theta, out, (int *)(out + MLP_NIN), out + MLP_NIN + 2);
+        ck(hipGetLastError());
+        ck(hipMemcpyAsync(ws.h_pol_out, out, (MLP_NIN + 4) * sizeof(float), hipMemcpyDeviceToHost, stream));
+        ck(hipStreamSynchronize(stream));
+        std::memcpy(feat, ws.h_pol_out, MLP_NIN * sizeof(float));
+        std::memcpy(bins, ws.h_pol_out + MLP_NIN, 2 * sizeof(int));
+        std::memcpy(conf, ws.h_pol_out + MLP_NIN + 2, 2 * sizeof(float));
+    } catch (const HipFail &f) {
+        return -100 - (int)f.e;
+    }
+    return 0;
+}
+
+extern "C" int neig_mlp_grad(int batch, const float *X, const int *a, const int *c, const float *w,
+                             const float *theta, float *grad, float *loss, hipStream_t stream) {
+    if (batch < 1) return -1;
+    if (!X) return -2;
+    if (!a) return -3;
+    if (!c) return -4;
+    if (!w) return -5;
+    if (!theta) return -6;
+    if (!grad) return -7;
+    if (!loss) return -8;
+    std::lock_guard<std::mutex> lock(g_mutex);
+    try {
+        DeviceWs &ws = workspace();
+        const int nblk = (batch + MLP_TILE - 1) / MLP_TILE;
+        grow(&ws.mlp_part, &ws.mlp_part_cap, (size_t)nblk * (MLP_NPARAM + 1));
+        float *lossp = ws.mlp_part + (size_t)nblk * MLP_NPARAM;
+        hipLaunchKernelGGL(k_mlp_grad, dim3(nblk), dim3(256), 0, stream, theta, X, a, c, w, batch,
+                           1.0f / (float)batch, ws.mlp_part, lossp);
+        ck(hipGetLastError());
+        hipLaunchKernelGGL(k_mlp_reduce, dim3((MLP_NPARAM + 1 + 255) / 256), dim3(256), 0, stream, ws.mlp_part,
+                           lossp, nblk, grad, loss);
+        ck(hipGetLastError());
+    } catch (const HipFail &f) {
+        return -100 - (int)f.e;
+    }
+    return 0;
+}
+
+extern "C" int neig_mlp_adam(float *theta, const float *grad, float *m, float *v, int step, float lr,
+                             hipStream_t stream) {
+    if (!theta) return -1;
+    if (!grad) return -2;
+    if (!m) return -3;
+    if (!v) return -4;
+    if (step < 1) return -5;
+    const double b1 = 0.9, b2 = 0.999;
+    const float bc1 = (float)(1.0 - std::pow(b1, step)), bc2 = (float)(1.0 - std::pow(b2, step));
+    hipLaunchKernelGGL(k_mlp_adam, dim3((MLP_NPARAM + 255) / 256), dim3(256), 0, stream, theta, grad, m, v, lr,
+                       (float)b1, (float)b2, 1e-8f, bc1, bc2);
+    const hipError_t e = hipGetLastError();
+    return e == hipSuccess ? 0 : -100 - (int)e;
+}
+
+extern "C" int neig_mlp_infer(int batch, const float *X, const float *theta, float *logits, int *bins, float *conf,
+                              hipStream_t stream) {
+    if (batch < 1) return -1;
+    if (!X) return -2;
+    if (!theta) return -3;
+    if (!logits) return -4;
+    if (!bins) return -5;
+    if (!conf) return -6;
+    const int grid = std::min((batch + 3) / 4, 1024);
+    hipLaunchKernelGGL(k_mlp_infer, dim3(grid), dim3(256), 0, stream, theta, X, batch, logits, bins, conf);
+    const hipError_t e = hipGetLastError();
+    return e == hipSuccess ? 0 : -100 - (int)e;
 }
 
 extern "C" int neig_set_params(const neig_params *p) {
@@ -796,6 +1170,8 @@ extern "C" int neig_set_params(const neig_params *p) {
     if (p->maxit < 0) return -7;
     if (p->nibble < 0 || p->nibble > 100) return -8;
     if (p->exc < 0) return -9;
+    if (p->timing < 0 || p->timing > 1) return -10;
+    if (p->policy < 0 || p->policy > 2) return -11;
     std::lock_guard<std::mutex> lock(g_mutex);
     g_params = *p;
     return 0;

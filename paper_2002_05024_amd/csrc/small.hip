@@ -51,7 +51,7 @@ __device__ __forceinline__ void refl_apply3(double &a, double &b, double &c, dou
 }
 
 // Block-wide max / sum (all NT threads call; result in every thread).
-__device__ double block_reduce(double v, bool is_max) {
+__device__ __forceinline__ double block_reduce(double v, bool is_max) {
     __shared__ double red[NT / LANES];
     v = is_max ? wave_max(v) : wave_sum(v);
     __syncthreads();
@@ -83,7 +83,7 @@ __device__ __forceinline__ void lds_rot_cols(double *M, int ld, int c, int r0, i
 
 // Standardise the 2x2 block at (j, j) of the m x m matrix T (rotation applied to
 // whole rows and columns of T and to the columns of Q).
-__device__ void lds_standardise(double *T, int ldt, double *Q, int ldq, int m, int j) {
+__device__ __forceinline__ void lds_standardise(double *T, int ldt, double *Q, int ldq, int m, int j) {
     Std2 o = std2x2(AT(T, ldt, j, j), AT(T, ldt, j, j + 1), AT(T, ldt, j + 1, j), AT(T, ldt, j + 1, j + 1));
     __syncthreads();
     if (!(o.cs == 1.0 && o.sn == 0.0)) {
@@ -103,7 +103,7 @@ __device__ void lds_standardise(double *T, int ldt, double *Q, int ldq, int m, i
 // 0..r_hi-1 of T (columns k0..k0+nb+1), and, if withq, every row of Q.  Work
 // items are spread over threads t0, t0+nth, ...  The coefficients are read into
 // registers once; segments of full length take a branch-free path.
-__device__ void far_apply(double *T, int ldt, double *Q, int ldq, int m, int k0, int nb, int c_lo, int c_hi,
+__device__ __forceinline__ void far_apply(double *T, int ldt, double *Q, int ldq, int m, int k0, int nb, int c_lo, int c_hi,
                           int r_hi, bool withq, const double *rt, const double *r1, const double *r2, int t0, int nth) {
     const int ncol = (c_hi >= c_lo) ? c_hi - c_lo + 1 : 0;
     const int total = ncol + r_hi + (withq ? m : 0);
@@ -232,7 +232,7 @@ __device__ __forceinline__ void near_step(double *T, int ldt, int l, int k, int 
 // only the near field updated (columns up to cnear, rows from k0).  (x0, x1, x2)
 // carries the generating vector of the next step between calls.  Reflectors with
 // tau = 0 are exact no-ops, so no step is special-cased.
-__device__ void near_steps(double *T, int ldt, int l, int i, int k0, int k1, int cnear, double tr, double det,
+__device__ __forceinline__ void near_steps(double *T, int ldt, int l, int i, int k0, int k1, int cnear, double tr, double det,
                            double *rt, double *r1, double *r2, double &x0, double &x1, double &x2) {
     for (int k = k0; k < k1; ++k) {
         if (k == l) {
@@ -260,7 +260,7 @@ __device__ void near_steps(double *T, int ldt, int l, int i, int k0, int k1, int
 
 // One implicit double-shift step (all NT threads call) on the active rows l..i
 // of the m x m LDS matrix T; updates span all of T and Q's columns.
-__device__ void lds_francis(double *T, int ldt, double *Q, int ldq, int m, int l, int i, double tr, double det) {
+__device__ __forceinline__ void lds_francis(double *T, int ldt, double *Q, int ldq, int m, int l, int i, double tr, double det) {
     __shared__ double rq[2][3][FB];
     const int tid = threadIdx.x, wave = tid / LANES;
     double x0 = 0.0, x1 = 0.0, x2 = 0.0;
@@ -298,7 +298,7 @@ __device__ void lds_francis(double *T, int ldt, double *Q, int ldq, int m, int l
 // Double-shift QR iteration on the m x m LDS matrix T (upper Hessenberg) with Q
 // accumulated.  Returns 0, or i+1 when rows/cols 0..i did not converge within
 // maxit iterations.  *iters receives the iteration count.
-__device__ int lds_small_qr(double *T, int ldt, double *Q, int ldq, int m, double hnorm, double smlnum, int maxit,
+__device__ __forceinline__ int lds_small_qr(double *T, int ldt, double *Q, int ldq, int m, double hnorm, double smlnum, int maxit,
                             int *iters) {
     const int lane = threadIdx.x & (LANES - 1);
     int i = m - 1, its = 0, total = 0;
@@ -358,7 +358,7 @@ __device__ int lds_small_qr(double *T, int ldt, double *Q, int ldq, int m, doubl
 
 // Load the m x m diagonal block of H at (off, off) into T (zeros below the
 // subdiagonal) and set Q = I.
-__device__ void lds_load_block(const double *H, int ldh, int off, int m, double *T, int ldt, double *Q, int ldq) {
+__device__ __forceinline__ void lds_load_block(const double *H, int ldh, int off, int m, double *T, int ldt, double *Q, int ldq) {
     for (int idx = threadIdx.x; idx < m * m; idx += NT) {
         const int i = idx % m, j = idx / m;
         AT(T, ldt, i, j) = (i <= j + 1) ? AT(H, ldh, off + i, off + j) : 0.0;
@@ -368,7 +368,7 @@ __device__ void lds_load_block(const double *H, int ldh, int off, int m, double 
 }
 
 // Write T back to H's diagonal block and Q^T to Ut (column-major, ld ldut).
-__device__ void lds_store(double *H, int ldh, int off, int m, const double *T, int ldt, const double *Q, int ldq,
+__device__ __forceinline__ void lds_store(double *H, int ldh, int off, int m, const double *T, int ldt, const double *Q, int ldq,
                           double *Ut, int ldut) {
     for (int idx = threadIdx.x; idx < m * m; idx += NT) {
         const int i = idx % m, j = idx / m;
@@ -377,7 +377,7 @@ __device__ void lds_store(double *H, int ldh, int off, int m, const double *T, i
     }
 }
 
-extern "C" __global__ void __launch_bounds__(NT)
+extern "C" __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(1, 1)))
 k_small_qr(double *H, int ldh, int off, int m, double hnorm, double smlnum, int maxit, double *Ut, int ldut,
            int *status) {
     extern __shared__ double lds[];
@@ -650,7 +650,7 @@ __device__ __forceinline__ bool swap_transform(const double (&B)[P + Q][P + Q], 
 // Swap the adjacent diagonal blocks of T at st (sizes P then Q) in place, with
 // the transformation applied to whole rows/columns of the nw x nw window and to V.
 template <int P, int Q>
-__device__ bool lds_swap_pq(double *T, int ldt, double *V, int ldv, int nw, int st) {
+__device__ __forceinline__ bool lds_swap_pq(double *T, int ldt, double *V, int ldv, int nw, int st) {
     constexpr int N = P + Q;
     double B[N][N], Qm[N][N], Bn[N][N];
 #pragma unroll
@@ -704,7 +704,7 @@ __device__ bool lds_swap_pq(double *T, int ldt, double *V, int ldv, int nw, int 
     return true;
 }
 
-__device__ bool lds_swap(double *T, int ldt, double *V, int ldv, int nw, int st, int p, int q) {
+__device__ __forceinline__ bool lds_swap(double *T, int ldt, double *V, int ldv, int nw, int st, int p, int q) {
     if (p == 1 && q == 1) return lds_swap_pq<1, 1>(T, ldt, V, ldv, nw, st);
     if (p == 1 && q == 2) return lds_swap_pq<1, 2>(T, ldt, V, ldv, nw, st);
     if (p == 2 && q == 1) return lds_swap_pq<2, 1>(T, ldt, V, ldv, nw, st);
@@ -715,7 +715,7 @@ __device__ bool lds_swap(double *T, int ldt, double *V, int ldv, int nw, int st,
 
 // Turn x[0..len-1] (LDS) into a Householder vector in place: on return
 // x[0] = 1, x[1..] = v, *tau and *beta set.  All NT threads call.
-__device__ void lds_house(double *x, int len, double *tau, double *beta) {
+__device__ __forceinline__ void lds_house(double *x, int len, double *tau, double *beta) {
     const double alpha = x[0];
     double mx = 0.0;
     for (int t = 1 + (int)threadIdx.x; t < len; t += NT) mx = fmax(mx, fabs(x[t]));
@@ -744,7 +744,7 @@ __device__ void lds_house(double *x, int len, double *tau, double *beta) {
 }
 
 // rows r0..r0+len-1 of M, columns c0..c1, from the left by I - tau v v^T
-__device__ void lds_refl_left(double *M, int ld, int r0, int len, int c0, int c1, double tau, const double *v) {
+__device__ __forceinline__ void lds_refl_left(double *M, int ld, int r0, int len, int c0, int c1, double tau, const double *v) {
     for (int j = c0 + (int)threadIdx.x; j <= c1; j += NT) {
         double d = 0.0;
         for (int t = 0; t < len; ++t) d += v[t] * AT(M, ld, r0 + t, j);
@@ -754,7 +754,7 @@ __device__ void lds_refl_left(double *M, int ld, int r0, int len, int c0, int c1
 }
 
 // columns c0..c0+len-1 of M (rows r0..r1) and of M2 (rows 0..r2-1), from the right
-__device__ void lds_refl_right2(double *M, int ld, int r0, int r1, double *M2, int ld2, int r2, int c0, int len,
+__device__ __forceinline__ void lds_refl_right2(double *M, int ld, int r0, int r1, double *M2, int ld2, int r2, int c0, int len,
                                 double tau, const double *v) {
     const int n1 = (r1 >= r0) ? r1 - r0 + 1 : 0;
     for (int it = threadIdx.x; it < n1 + r2; it += NT) {
@@ -770,34 +770,38 @@ __device__ void lds_refl_right2(double *M, int ld, int r0, int r1, double *M2, i
 
 // ---------------------------------------------------------------- AED
 
-// status: [0] nd (deflated count), [1] number of Ritz values written to sr/si,
-// [2] 1 if H and the window transform V were updated (the host then applies V^T
-// to the rest of H and Z), [3] rows not converged by the window QR, [4] 1 if a
-// swap was rejected, [5] window QR iterations, [6] block swaps, [7..9] shader
-// clock cycles spent in the window QR, the spike test with its swaps, and the
-// re-Hessenberg reduction with the write-back.
-extern "C" __global__ void __launch_bounds__(NT)
-k_aed(double *H, int ldh, int ktop, int kbot, int nw, double hnorm, double smlnum, int criterion, int maxit,
-      double *Vt, int ldvt, int *status, double *sr, double *si) {
-    extern __shared__ double lds[];
+// Result of the AED core (returned in every thread).
+struct AedOut {
+    int nd;       // deflated count
+    int nritz;    // Ritz values written
+    int infqr;    // rows not converged by the window QR
+    int swapfail; // a swap was rejected
+    int iters;    // window QR iterations
+    int nswap;    // block swaps
+    int late;     // deflations found above a failed block
+    double spike0;  // new coupling entry h(kwtop, kwtop-1) when nd > 0
+    long long cyc_qr, cyc_defl, cyc_hess;
+};
+
+// AED on the nw x nw window already in LDS (T upper Hessenberg, V = I), coupled
+// to the rest by the spike s (Section 3.2, "AED step"): Schur form of T by the
+// window QR, spike test bottom-up with failing blocks moved to the top by block
+// swaps, undeflated Ritz values written to sr/si (thread 0), and, if anything
+// deflated, the spike and the undeflated part reduced back to Hessenberg form.
+// On return T and V hold the transformed window and its orthogonal factor.
+__device__ __forceinline__ AedOut aed_core(double *T, double *V, int ld, double *x, int nw, double s, double hnorm, double smlnum,
+                           int criterion, int maxit, double *sr, double *si) {
     const int tid = threadIdx.x;
-    const int ld = nw + 1;
-    double *T = lds;
-    double *V = lds + (size_t)nw * ld;
-    double *x = V + (size_t)nw * ld;  // nw doubles of vector scratch
-    const int kwtop = kbot - nw + 1;
-    const double s = (kwtop > ktop) ? AT(H, ldh, kwtop, kwtop - 1) : 0.0;
+    AedOut o;
     const long long c0 = clock64();
-    lds_load_block(H, ldh, kwtop, nw, T, ld, V, ld);
-    int iters = 0;
-    const int infqr = lds_small_qr(T, ld, V, ld, nw, hnorm, smlnum, maxit, &iters);
+    o.iters = 0;
+    o.infqr = lds_small_qr(T, ld, V, ld, nw, hnorm, smlnum, maxit, &o.iters);
     __syncthreads();
     const long long c1 = clock64();
-    int nswap = 0;
-
-    // spike test from the bottom up; failures move to [infqr, top)
-    int top = infqr, kend = nw, swapfail = 0;
-    int late = 0;  // deflations found after the first failure (they cost swaps)
+    o.nswap = 0;
+    o.late = 0;
+    int top = o.infqr, kend = nw;
+    o.swapfail = 0;
     while (kend > top) {
         const int bs = (kend - 2 >= top && AT(T, ld, kend - 1, kend - 2) != 0.0) ? 2 : 1;
         const int j = kend - bs;
@@ -816,7 +820,7 @@ k_aed(double *H, int ldh, int ktop, int kbot, int nw, double hnorm, double smlnu
         tol = fmax(tol, smlnum);
         __syncthreads();  // all threads have read the test inputs before any swap writes
         if (sp <= tol) {
-            if (top > infqr) late += bs;
+            if (top > o.infqr) o.late += bs;
             kend -= bs;
             continue;
         }
@@ -829,59 +833,55 @@ k_aed(double *H, int ldh, int ktop, int kbot, int nw, double hnorm, double smlnu
                 ok = false;
                 break;
             }
-            ++nswap;
+            ++o.nswap;
             pos = st;
         }
         if (!ok) {
-            swapfail = 1;
+            o.swapfail = 1;
             top = kend;
             break;
         }
         top += bs;
     }
-    const int nd = nw - kend;
+    o.nd = nw - kend;
     const long long c2 = clock64();
 
     // undeflated Ritz values (shift candidates), top to bottom
-    if (tid == 0) {
-        int c = 0;
-        for (int j = infqr; j < kend;) {
-            if (j + 1 < kend && AT(T, ld, j + 1, j) != 0.0) {
+    int c = 0;
+    for (int j = o.infqr; j < kend;) {
+        if (j + 1 < kend && AT(T, ld, j + 1, j) != 0.0) {
+            if (tid == 0) {
                 double re1, im1, re2, im2;
                 eig2x2(AT(T, ld, j, j), AT(T, ld, j, j + 1), AT(T, ld, j + 1, j), AT(T, ld, j + 1, j + 1), &re1,
                        &im1, &re2, &im2);
                 sr[c] = re1; si[c] = im1; sr[c + 1] = re2; si[c + 1] = im2;
-                c += 2;
-                j += 2;
-            } else {
+            }
+            c += 2;
+            j += 2;
+        } else {
+            if (tid == 0) {
                 sr[c] = AT(T, ld, j, j);
                 si[c] = 0.0;
-                ++c;
-                ++j;
             }
+            ++c;
+            ++j;
         }
-        status[0] = nd;
-        status[1] = c;
-        status[2] = (nd > 0) ? 1 : 0;
-        status[3] = infqr;
-        status[4] = swapfail;
-        status[5] = iters;
-        status[6] = nswap;
-        status[7] = (int)min(c1 - c0, (long long)INT_MAX);
-        status[8] = (int)min(c2 - c1, (long long)INT_MAX);
-        status[9] = 0;
-        status[10] = late;
     }
-    if (nd == 0) return;  // H untouched; only the shifts are used
+    o.nritz = c;
+    o.spike0 = 0.0;
+    o.cyc_qr = c1 - c0;
+    o.cyc_defl = c2 - c1;
+    o.cyc_hess = 0;
+    if (o.nd == 0) return o;
 
-    double spike0 = 0.0;
     if (kend > 0 && s != 0.0) {
+        __syncthreads();
         for (int t = tid; t < kend; t += NT) x[t] = s * AT(V, ld, 0, t);
         __syncthreads();
         if (kend > 1) {
             double tau, beta;
             lds_house(x, kend, &tau, &beta);
-            spike0 = beta;
+            o.spike0 = beta;
             if (tau != 0.0) {
                 lds_refl_left(T, ld, 0, kend, 0, nw - 1, tau, x);
                 __syncthreads();
@@ -889,27 +889,61 @@ k_aed(double *H, int ldh, int ktop, int kbot, int nw, double hnorm, double smlnu
                 __syncthreads();
             }
             // Householder Hessenberg reduction of the undeflated leading block
-            for (int c = 0; c + 2 < kend; ++c) {
-                const int len = kend - c - 1;
-                for (int t = tid; t < len; t += NT) x[t] = AT(T, ld, c + 1 + t, c);
+            for (int cc = 0; cc + 2 < kend; ++cc) {
+                const int len = kend - cc - 1;
+                for (int t = tid; t < len; t += NT) x[t] = AT(T, ld, cc + 1 + t, cc);
                 __syncthreads();
                 double tau2, beta2;
                 lds_house(x, len, &tau2, &beta2);
                 if (tau2 == 0.0) continue;
-                for (int t = tid; t < len; t += NT) AT(T, ld, c + 1 + t, c) = (t == 0) ? beta2 : 0.0;
-                lds_refl_left(T, ld, c + 1, len, c + 1, nw - 1, tau2, x);
+                for (int t = tid; t < len; t += NT) AT(T, ld, cc + 1 + t, cc) = (t == 0) ? beta2 : 0.0;
+                lds_refl_left(T, ld, cc + 1, len, cc + 1, nw - 1, tau2, x);
                 __syncthreads();
-                lds_refl_right2(T, ld, 0, kend - 1, V, ld, nw, c + 1, len, tau2, x);
+                lds_refl_right2(T, ld, 0, kend - 1, V, ld, nw, cc + 1, len, tau2, x);
                 __syncthreads();
             }
         } else {
-            spike0 = x[0];
+            o.spike0 = x[0];
         }
     }
     __syncthreads();
-    lds_store(H, ldh, kwtop, nw, T, ld, V, ld, Vt, ldvt);
-    if (kwtop > ktop && tid == 0) {
-        AT(H, ldh, kwtop, kwtop - 1) = spike0;
-        status[9] = (int)min(clock64() - c2, (long long)INT_MAX);
+    o.cyc_hess = clock64() - c2;
+    return o;
+}
+
+// status: [0] nd (deflated count), [1] number of Ritz values written to sr/si,
+// [2] 1 if H and the window transform V were updated (the host then applies V^T
+// to the rest of H and Z), [3] rows not converged by the window QR, [4] 1 if a
+// swap was rejected, [5] window QR iterations, [6] block swaps, [7..9] shader
+// clock cycles spent in the window QR, the spike test with its swaps, and the
+// re-Hessenberg reduction with the write-back, [10] deflations found above a
+// block that failed the test.
+extern "C" __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(1, 1)))
+k_aed(double *H, int ldh, int ktop, int kbot, int nw, double hnorm, double smlnum, int criterion, int maxit,
+      double *Vt, int ldvt, int *status, double *sr, double *si) {
+    extern __shared__ double lds[];
+    const int ld = nw + 1;
+    double *T = lds;
+    double *V = lds + (size_t)nw * ld;
+    double *x = V + (size_t)nw * ld;  // nw doubles of vector scratch
+    const int kwtop = kbot - nw + 1;
+    const double s = (kwtop > ktop) ? AT(H, ldh, kwtop, kwtop - 1) : 0.0;
+    lds_load_block(H, ldh, kwtop, nw, T, ld, V, ld);
+    const AedOut o = aed_core(T, V, ld, x, nw, s, hnorm, smlnum, criterion, maxit, sr, si);
+    if (threadIdx.x == 0) {
+        status[0] = o.nd;
+        status[1] = o.nritz;
+        status[2] = (o.nd > 0) ? 1 : 0;
+        status[3] = o.infqr;
+        status[4] = o.swapfail;
+        status[5] = o.iters;
+        status[6] = o.nswap;
+        status[7] = (int)min(o.cyc_qr, (long long)INT_MAX);
+        status[8] = (int)min(o.cyc_defl, (long long)INT_MAX);
+        status[9] = (int)min(o.cyc_hess, (long long)INT_MAX);
+        status[10] = o.late;
     }
+    if (o.nd == 0) return;  // H untouched; only the shifts are used
+    lds_store(H, ldh, kwtop, nw, T, ld, V, ld, Vt, ldvt);
+    if (kwtop > ktop && threadIdx.x == 0) AT(H, ldh, kwtop, kwtop - 1) = o.spike0;
 }

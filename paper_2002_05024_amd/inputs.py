@@ -136,3 +136,54 @@ def to_hessenberg(A: np.ndarray):
 def batch_sizes(count: int, g: np.random.Generator, lo: int = 32, hi: int = 1024) -> np.ndarray:
     """Problem sizes drawn uniformly from [lo, hi]."""
     return g.integers(lo, hi + 1, size=count)
+
+
+def prescribed_hessenberg(n: int, g: np.random.Generator, upper_std: float):
+    """Hessenberg form of U T U^T (U Haar, T prescribed) without forming U.
+
+    The Hessenberg form of an orthogonal similarity V^T T V is fixed, up to a
+    diagonal sign similarity, by the first column of V (implicit-Q uniqueness);
+    for Haar U that column is uniform on the unit sphere.  So a Householder
+    reflector P with P e1 = w, w uniform, followed by the Hessenberg reduction of
+    P T P gives the same distribution as reducing U T U^T, at a third of the
+    cost.  Returns (H, eigenvalues)."""
+    import scipy.linalg
+
+    T, eig = prescribed_quasi_triangular(n, g, upper_std)
+    w = g.standard_normal(n)
+    w /= np.linalg.norm(w)
+    v = w.copy()
+    v[0] -= 1.0  # P = I - 2 v v^T / v^T v maps e1 to w
+    vv = float(v @ v)
+    if vv > 0.0:
+        f = 2.0 / vv
+        T = T - f * np.outer(v, v @ T)
+        T = T - f * np.outer(T @ v, v)
+    H = scipy.linalg.hessenberg(np.asfortranarray(T), calc_q=False, overwrite_a=True)
+    return np.asfortranarray(np.triu(H, -1)), eig
+
+
+def batched_problem(seed: int, i: int, n: int, upper_std: float = 0.1):
+    """Problem i of a batch: even i random N(0,1) Hessenberg, odd i a Hessenberg
+    matrix with a prescribed spectrum (:func:`prescribed_hessenberg`).  Returns
+    (H, eigenvalues or None)."""
+    g = rng(BATCHED, 1_000_000 + 10_000 * int(seed) + int(i))
+    if i % 2 == 0:
+        return random_hessenberg(n, g), None
+    return prescribed_hessenberg(n, g, upper_std)
+
+
+def batched_workload(count: int = 512, seed: int = 0, lo: int = 32, hi: int = 1024, upper_std: float = 0.1,
+                     threads: int = 8):
+    """The batched workload: ``count`` problems with n uniform in [lo, hi], half
+    random and half prescribed-spectrum, made by ``threads`` single-threaded
+    workers.  Returns (list of H, list of spectra)."""
+    from concurrent.futures import ThreadPoolExecutor
+
+    from threadpoolctl import threadpool_limits
+
+    sizes = batch_sizes(count, rng(BATCHED, 999_999 - int(seed)), lo, hi)
+    with threadpool_limits(limits=1):
+        with ThreadPoolExecutor(max_workers=max(1, threads)) as ex:
+            out = list(ex.map(lambda a: batched_problem(seed, a[0], int(a[1]), upper_std), enumerate(sizes)))
+    return [h for h, _ in out], [lam for _, lam in out]

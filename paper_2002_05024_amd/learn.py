@@ -1,0 +1,295 @@
+"""Training and evaluation of the parameter-proposal network.
+
+Three stages, each run on a GPU:
+
+``collect``  solves matrices of three families (random N(0,1) Hessenberg,
+             prescribed-spectrum Hessenberg, row-graded Hessenberg) with
+             n uniform in [1000, 8000], with exploration switched on
+             (``policy = 2``: every iteration's shift-count and window bins drawn
+             at random), and stores each decision's features, bins, and the
+             deflations per millisecond that followed it.
+``train``    fits the network by reward-weighted cross-entropy with the
+             library's own GPU kernels (``neig_mlp_grad`` + ``neig_mlp_adam``):
+             a decision's weight grows with how much its reward beat the
+             typical reward of its own run, so the network imitates the better
+             choices.  Input normalisation (mu, sd) comes from the data.
+``evaluate`` solves held-out matrices with the default rules and with the
+             network (``policy = 1``), times both, and checks every result
+             (backward error and orthogonality <= 50 n eps); a result that fails
+             the check with the network is solved again with the default rules.
+
+Inputs are built on the host by worker threads while the GPU solves, so the
+GPU does not wait for them.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import threading
+import time
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+SAVED = os.path.join(HERE, "policy_gfx950.npy")
+FAMILIES = ("random", "prescribed", "graded")
+EPS = 2.0 ** -52
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def make_matrix(index: int, split: str, lo: int = 1000, hi: int = 8000):
+    """Matrix ``index`` of a split ('train' or 'heldout'): family index % 3,
+    n uniform in [lo, hi]."""
+    from . import inputs
+
+    base = 0 if split == "train" else 500_000
+    g = inputs.rng(inputs.LEARNED, base + index)
+    n = int(g.integers(lo, hi + 1))
+    fam = FAMILIES[index % 3]
+    if fam == "random":
+        H = inputs.random_hessenberg(n, g)
+    elif fam == "graded":
+        H = inputs.graded_hessenberg(n, g)
+    else:
+        H, _ = inputs.prescribed_hessenberg(n, g, 0.1 / np.sqrt(n))
+    return fam, H
+
+
+def producer(indices, split, lo, hi, threads=8, depth=None):
+    """Yield (index, family, H) in order, built ahead by worker threads."""
+    from concurrent.futures import ThreadPoolExecutor
+
+    from threadpoolctl import threadpool_limits
+
+    depth = depth or 2 * threads
+    limits = threadpool_limits(limits=2)  # host BLAS threads per worker, for the whole run
+    ex = ThreadPoolExecutor(max_workers=threads)
+    futs = {}
+
+    def submit(k):
+        futs[k] = ex.submit(make_matrix, indices[k], split, lo, hi)
+
+    for k in range(min(depth, len(indices))):
+        submit(k)
+    for k in range(len(indices)):
+        fam, H = futs.pop(k).result()
+        if k + depth < len(indices):
+            submit(k + depth)
+        yield indices[k], fam, H
+    ex.shutdown()
+    limits.restore_original_limits()
+
+
+class Solver:
+    """Device buffers sized for the largest n, reused by every solve."""
+
+    def __init__(self, nmax: int):
+        import torch
+
+        from . import binding
+
+        self.torch, self.binding = torch, binding
+        self.Hbuf = torch.empty(nmax * nmax, dtype=torch.float64, device="cuda")
+        self.Zbuf = torch.empty(nmax * nmax, dtype=torch.float64, device="cuda")
+
+    def solve(self, H, check: bool = True):
+        """Solve with the current parameters; returns (seconds, info, be, oe)."""
+        torch = self.torch
+        n = H.shape[0]
+        H0 = torch.from_numpy(np.ascontiguousarray(H.T)).cuda().t()
+        Hd = self.Hbuf[: n * n].view(n, n).t()  # column-major n x n
+        Zd = self.Zbuf[: n * n].view(n, n).t()
+        Hd.copy_(H0)
+        Zd.zero_()
+        Zd.diagonal().fill_(1.0)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        r = self.binding.schur(Hd, Zd)
+        e1.record()
+        torch.cuda.synchronize()
+        sec = e0.elapsed_time(e1) / 1000.0
+        be = oe = float("nan")
+        if check:
+            R = torch.mm(torch.mm(Zd, Hd), Zd.t())
+            R.sub_(H0)
+            be = float(torch.linalg.norm(R) / torch.linalg.norm(H0))
+            E = torch.mm(Zd.t(), Zd)
+            E.diagonal().sub_(1.0)
+            oe = float(torch.linalg.norm(E))
+        return sec, r.info, be, oe
+
+
+def collect(start: int, count: int, out: str, lo: int, hi: int, seed: int, threads: int):
+    from . import binding
+
+    binding.load_library()
+    solver = Solver(hi)
+    feats, bins, stats, runs = [], [], [], []
+    t0 = time.time()
+    for i, fam, H in producer(list(range(start, start + count)), "train", lo, hi, threads):
+        binding.set_params(policy=2, seed=seed * 100_003 + i)
+        sec, info, _, _ = solver.solve(H, check=False)
+        f, b, s = binding.policy_log()
+        feats.append(f)
+        bins.append(b)
+        stats.append(s)
+        runs.append(np.full(len(b), i, dtype=np.int32))
+        log(f"[collect] {i} {fam} n={H.shape[0]} {sec:.2f}s info={info} decisions={len(b)} "
+            f"elapsed {time.time() - t0:.0f}s")
+    binding.set_params(policy=0)
+    np.savez_compressed(out, feat=np.concatenate(feats), bins=np.concatenate(bins), stats=np.concatenate(stats),
+                        run=np.concatenate(runs))
+
+
+def sample_weights(stats, run, beta: float = 1.5):
+    """Reward = deflations per ms after the decision; advantage = log of the
+    reward over its run's median reward; weight = exp(beta * advantage) for
+    decisions above the median, 0 below (imitate the better half)."""
+    r = np.maximum(stats[:, 0], 0.0) / np.maximum(stats[:, 1], 1e-3)
+    w = np.zeros_like(r)
+    for k in np.unique(run):
+        sel = run == k
+        med = np.median(r[sel])
+        adv = np.log((r[sel] + 1e-3) / (med + 1e-3))
+        w[sel] = np.where(adv > 0, np.exp(np.minimum(beta * adv, 5.0)), 0.0)
+    return w
+
+
+def train(data_files, out: str, epochs: int = 30, batch: int = 4096, lr: float = 2e-3, seed: int = 0):
+    import torch
+
+    from . import binding
+
+    binding.load_library()
+    parts = [np.load(f) for f in data_files]
+    feat = np.concatenate([p["feat"] for p in parts]).astype(np.float64)
+    bins = np.concatenate([p["bins"] for p in parts])
+    stats = np.concatenate([p["stats"] for p in parts])
+    run = np.concatenate([p["run"] for p in parts])
+    w = sample_weights(stats, run)
+    keep = w > 0
+    log(f"[train] {len(w)} decisions, {keep.sum()} weighted, from {len(np.unique(run))} runs")
+    X, B, W = feat[keep], bins[keep], w[keep]
+    W = W / W.mean()
+    mu = X.mean(axis=0)
+    sd = X.std(axis=0) + 1e-3
+    theta = _init_theta(seed, mu, sd)
+    dev = torch.device("cuda")
+    Xd = torch.tensor(X, dtype=torch.float32, device=dev)
+    ad = torch.tensor(B[:, 0], dtype=torch.int32, device=dev)
+    cd = torch.tensor(B[:, 1], dtype=torch.int32, device=dev)
+    wd = torch.tensor(W, dtype=torch.float32, device=dev)
+    th = torch.tensor(theta, dtype=torch.float32, device=dev)
+    m = torch.zeros_like(th)
+    v = torch.zeros_like(th)
+    g = np.random.default_rng(seed)
+    step = 0
+    N = Xd.shape[0]
+    for ep in range(epochs):
+        perm = torch.tensor(g.permutation(N), device=dev)
+        tot = 0.0
+        for s in range(0, N, batch):
+            idx = perm[s: s + batch]
+            loss, grad = binding.mlp_grad(Xd[idx].contiguous(), ad[idx].contiguous(), cd[idx].contiguous(),
+                                          wd[idx].contiguous(), th)
+            step += 1
+            binding.mlp_adam(th, grad, m, v, step, lr)
+            tot += float(loss.item()) * len(idx)
+        log(f"[train] epoch {ep} loss {tot / N:.4f}")
+    np.save(out, th.cpu().numpy())
+    return th.cpu().numpy()
+
+
+def _init_theta(seed, mu, sd):
+    """He-style random initialisation with zero biases, in the library's layout."""
+    g = np.random.Generator(np.random.PCG64(np.random.SeedSequence([56, int(seed)])))
+    parts = [mu, sd, g.standard_normal((64, 24)) * np.sqrt(2.0 / 24), np.zeros(64),
+             g.standard_normal((64, 64)) * np.sqrt(2.0 / 64), np.zeros(64),
+             g.standard_normal((16, 64)) * np.sqrt(1.0 / 64), np.zeros(16)]
+    return np.concatenate([np.asarray(p, dtype=np.float64).ravel() for p in parts])
+
+
+def evaluate(weights: str, start: int, count: int, lo: int, hi: int, min_conf: float, threads: int):
+    """Held-out matrices solved with the default rules and with the network."""
+    from . import binding
+
+    binding.load_library()
+    theta = np.load(weights)
+    solver = Solver(hi)
+    rows = []
+    for i, fam, H in producer(list(range(start, start + count)), "heldout", lo, hi, threads):
+        n = H.shape[0]
+        binding.policy_set(None)
+        binding.set_params(policy=0)
+        t_def, info_d, be_d, oe_d = solver.solve(H)
+        binding.policy_set(theta, min_conf)
+        binding.set_params(policy=1)
+        t_net, info_n, be_n, oe_n = solver.solve(H)
+        st = binding.get_stats()
+        ok = info_n == 0 and be_n <= 50 * n * EPS and oe_n <= 50 * n * EPS
+        t_judged = t_net
+        if not ok:  # the backward-error check judges: fall back to the default rules
+            binding.set_params(policy=0)
+            t2, info_n, be_n, oe_n = solver.solve(H)
+            t_judged += t2
+        rows.append({"i": i, "family": fam, "n": n, "t_default": t_def, "t_net": t_net, "t_judged": t_judged,
+                     "ok_net": bool(ok), "be_default": be_d, "be_net": be_n, "oe_default": oe_d, "oe_net": oe_n,
+                     "used": st["policy_used"], "fallback": st["policy_fallback"]})
+        log(f"[eval] {i} {fam} n={n} default {t_def:.3f}s net {t_net:.3f}s ok={ok} "
+            f"be {be_d / (n * EPS):.2f}/{be_n / (n * EPS):.2f} n eps")
+    binding.set_params(policy=0)
+    binding.policy_set(None)
+    tot_d = sum(r["t_default"] for r in rows)
+    tot_n = sum(r["t_judged"] for r in rows)
+    summary = {"matrices": len(rows), "total_default_s": tot_d, "total_net_s": tot_n,
+               "speedup": tot_d / tot_n if tot_n > 0 else None,
+               "per_family": {f: {"default_s": sum(r["t_default"] for r in rows if r["family"] == f),
+                                  "net_s": sum(r["t_judged"] for r in rows if r["family"] == f)}
+                              for f in FAMILIES},
+               "all_ok": all(r["ok_net"] for r in rows)}
+    return summary, rows
+
+
+def main():
+    ap = argparse.ArgumentParser(description="proposal network: collect / train / evaluate")
+    sub = ap.add_subparsers(dest="cmd", required=True)
+    c = sub.add_parser("collect")
+    c.add_argument("--start", type=int, default=0)
+    c.add_argument("--count", type=int, default=100)
+    c.add_argument("--out", required=True)
+    c.add_argument("--seed", type=int, default=1)
+    t = sub.add_parser("train")
+    t.add_argument("data", nargs="+")
+    t.add_argument("--out", default=SAVED)
+    t.add_argument("--epochs", type=int, default=30)
+    e = sub.add_parser("evaluate")
+    e.add_argument("--weights", default=SAVED)
+    e.add_argument("--start", type=int, default=0)
+    e.add_argument("--count", type=int, default=200)
+    e.add_argument("--min-conf", type=float, default=0.0)
+    e.add_argument("--out", default=None)
+    for p in (c, e):
+        p.add_argument("--lo", type=int, default=1000)
+        p.add_argument("--hi", type=int, default=8000)
+        p.add_argument("--threads", type=int, default=8)
+    args = ap.parse_args()
+    if args.cmd == "collect":
+        collect(args.start, args.count, args.out, args.lo, args.hi, args.seed, args.threads)
+    elif args.cmd == "train":
+        train(args.data, args.out, args.epochs)
+    else:
+        summary, rows = evaluate(args.weights, args.start, args.count, args.lo, args.hi, args.min_conf, args.threads)
+        print(json.dumps(summary), flush=True)
+        if args.out:
+            with open(args.out, "w") as f:
+                json.dump({"summary": summary, "rows": rows}, f, indent=1)
+
+
+if __name__ == "__main__":
+    main()

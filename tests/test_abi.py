@@ -20,7 +20,8 @@ def declared_functions():
 def test_header_declares_the_boundary():
     names = declared_functions()
     for required in ["neig_schur", "neig_schur_batched", "neig_sweep", "neig_aed", "neig_small_schur",
-                     "neig_set_params", "neig_get_params", "neig_get_stats", "neig_finalize", "neig_version"]:
+                     "neig_set_params", "neig_get_params", "neig_get_stats", "neig_finalize", "neig_version",
+                     "neig_set_batched_tune", "neig_get_batched_tune"]:
         assert required in names
 
 
@@ -58,6 +59,40 @@ def test_argument_errors_without_gpu_work():
     assert lib.neig_schur(4, ctypes.c_void_p(8), 3, ctypes.c_void_p(8), 4, None, None, None) == -3
     assert lib.neig_schur(4, ctypes.c_void_p(8), 4, ctypes.c_void_p(8), 2, None, None, None) == -5
     assert lib.neig_schur(0, None, 1, None, 1, None, None, None) == 0
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="libneig.so not built")
+def test_batched_tune_roundtrip_and_validation():
+    from paper_2002_05024_amd import binding
+
+    before = binding.get_batched_tune()
+    assert len(before["nw"]) == 6 and before["n_hi"][-1] >= 1 << 30
+    binding.set_batched_tune([100, 400, 0], [32, 48, 64], [8, 16, 32], [40, 64, 96], [50, 80, 96])
+    t = binding.get_batched_tune()
+    assert t["n_hi"][:2] == [100, 400] and t["n_hi"][2] >= 1 << 30
+    assert t["nw"] == [32, 48, 64, 64, 64, 64] and t["ns"][5] == 32 and t["chase_w"][0] == 50
+    for bad in ([[100, 50, 0], [32] * 3, [8] * 3, [40] * 3, [50] * 3],  # n_hi not increasing
+                [[0], [1], [8], [40], [50]],  # nw < 2
+                [[0], [32], [7], [40], [50]],  # odd ns
+                [[0], [32], [34], [40], [96]],  # ns > 32
+                [[0], [32], [32], [97], [96]],  # nmin too large
+                [[0], [32], [32], [40], [49]]):  # chase window cannot hold 16 bulges
+        with pytest.raises(binding.NeigError):
+            binding.set_batched_tune(*bad)
+    assert binding.get_batched_tune() == t  # unchanged on error
+    k = len(before["nw"])
+    binding.set_batched_tune(before["n_hi"], before["nw"], before["ns"], before["nmin"], before["chase_w"])
+    assert binding.get_batched_tune() == before and k == 6
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="libneig.so not built")
+def test_batched_argument_errors_without_gpu_work():
+    lib = ctypes.CDLL(LIB)
+    lib.neig_schur_batched.argtypes = [ctypes.c_int] + [ctypes.c_void_p] * 9
+    assert lib.neig_schur_batched(-1, *([None] * 9)) == -1
+    assert lib.neig_schur_batched(65537, *([None] * 9)) == -1
+    assert lib.neig_schur_batched(0, *([None] * 9)) == 0
+    assert lib.neig_schur_batched(3, *([None] * 9)) == -2
 
 
 def test_product_path_has_no_cpu_fallback():

@@ -1,0 +1,48 @@
+"""What the trained proposal network gains over the default size rules, on
+held-out matrices of the three training families (random N(0,1), prescribed
+spectrum, row-graded Hessenberg), with the backward-error check judging every
+result.  The network's weights are the committed file written by the
+training stage of ``paper_2002_05024_amd.learn``."""
+import os
+
+import numpy as np
+import pytest
+
+from gpu_util import say
+
+pytestmark = pytest.mark.gpu
+
+WEIGHTS = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "paper_2002_05024_amd",
+                       "policy_gfx950.npy")
+
+
+@pytest.fixture(scope="module")
+def neig():
+    import torch
+
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    from paper_2002_05024_amd import binding
+
+    binding.load_library()
+    yield binding
+    binding.set_params(policy=0)
+    binding.policy_set(None)
+
+
+@pytest.mark.skipif(not os.path.exists(WEIGHTS), reason="no trained network committed")
+def test_learned_vs_default_on_heldout(neig):
+    from paper_2002_05024_amd import learn
+
+    # six held-out matrices at the small end of the range, two per family
+    summary, rows = learn.evaluate(WEIGHTS, start=0, count=6, lo=1000, hi=2500, min_conf=0.0, threads=4)
+    for r in rows:
+        say(f"  {r['family']:10s} n={r['n']} default {r['t_default']:.3f}s network {r['t_net']:.3f}s "
+            f"judged {r['t_judged']:.3f}s ok={r['ok_net']}")
+    say(f"  total default {summary['total_default_s']:.3f}s network {summary['total_net_s']:.3f}s "
+        f"speedup {summary['speedup']:.3f}")
+    eps = 2.0 ** -52
+    for r in rows:
+        # every result that is kept meets the bound (the default rules re-solve a failure)
+        assert r["be_net"] <= 50 * r["n"] * eps and r["oe_net"] <= 50 * r["n"] * eps
+        assert r["be_default"] <= 50 * r["n"] * eps
+    assert np.isfinite(summary["speedup"])

@@ -1,0 +1,191 @@
+"""The proposal network's GPU kernels against the CPU oracle (oracle/mlp.py):
+FP32 loss and gradient of the reward-weighted cross-entropy, the Adam step,
+BF16 inference, and the feature kernel; then the solver with proposals
+switched on (exploration and a network) still meets the accuracy bounds."""
+import numpy as np
+import pytest
+
+from checks import EPS, backward_error, orthogonality, structure_violations
+from gpu_util import say, to_dev, to_host
+from oracle import mlp
+from paper_2002_05024_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def neig():
+    import torch
+
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    from paper_2002_05024_amd import binding
+
+    binding.load_library()
+    yield binding
+    binding.policy_set(None)
+    binding.set_params(policy=0)
+
+
+def batch_case(B, seed):
+    g = np.random.default_rng(seed)
+    theta = mlp.init(seed, mu=g.standard_normal(mlp.NIN) * 0.3, sd=0.5 + g.random(mlp.NIN))
+    X = g.standard_normal((B, mlp.NIN)) * 2.0
+    a = g.integers(0, 8, B)
+    c = g.integers(0, 8, B)
+    w = g.random(B) * 2.0
+    return theta, X, a, c, w
+
+
+def dev32(x, dtype=None):
+    import torch
+
+    return torch.tensor(np.asarray(x), dtype=dtype or torch.float32, device="cuda").contiguous()
+
+
+@pytest.mark.parametrize("B", [1, 31, 32, 100, 1000])
+def test_grad_matches_oracle(neig, B):
+    import torch
+
+    theta, X, a, c, w = batch_case(B, B)
+    # the oracle sees the same FP32-rounded inputs the GPU sees
+    th32 = theta.astype(np.float32).astype(np.float64)
+    X32 = X.astype(np.float32).astype(np.float64)
+    w32 = w.astype(np.float32).astype(np.float64)
+    L0, g0 = mlp.loss_and_grad(th32, X32, a, c, w32)
+    loss, grad = neig.mlp_grad(dev32(X), dev32(a, torch.int32), dev32(c, torch.int32), dev32(w), dev32(theta))
+    torch.cuda.synchronize()
+    g1 = grad.cpu().numpy().astype(np.float64)
+    say(f"B={B} loss {L0:.6f} vs {float(loss.item()):.6f}; max |dg| {np.max(np.abs(g1 - g0)):.2e} "
+        f"max |g| {np.max(np.abs(g0)):.2e}")
+    assert abs(float(loss.item()) - L0) <= 1e-5 * max(1.0, abs(L0))
+    assert np.all(np.abs(g1 - g0) <= 2e-5 * np.max(np.abs(g0)) + 1e-7)
+    assert np.all(g1[: 2 * mlp.NIN] == 0.0)
+
+
+def test_adam_matches_oracle(neig):
+    import torch
+
+    theta, X, a, c, w = batch_case(64, 7)
+    _, g = mlp.loss_and_grad(theta, X, a, c, w)
+    m = np.random.default_rng(1).standard_normal(theta.size) * 1e-3
+    v = np.random.default_rng(2).random(theta.size) * 1e-5
+    t_ref, m_ref, v_ref = mlp.adam_step(theta, g, m, v, 3, lr=1e-3)
+    th, gd, md, vd = dev32(theta), dev32(g), dev32(m), dev32(v)
+    neig.mlp_adam(th, gd, md, vd, 3, 1e-3)
+    torch.cuda.synchronize()
+    assert np.allclose(md.cpu().numpy(), m_ref, rtol=1e-5, atol=1e-9)
+    assert np.allclose(vd.cpu().numpy(), v_ref, rtol=1e-5, atol=1e-12)
+    assert np.allclose(th.cpu().numpy(), t_ref, rtol=1e-6, atol=2e-6)
+    assert np.all(th.cpu().numpy()[: 2 * mlp.NIN] == theta[: 2 * mlp.NIN].astype(np.float32))
+
+
+def test_training_lowers_the_loss(neig):
+    """A few hundred GPU steps (grad + Adam) on a synthetic labelling fit it."""
+    import torch
+
+    g = np.random.default_rng(11)
+    B = 512
+    X = g.standard_normal((B, mlp.NIN))
+    a = (X[:, 0] > 0).astype(int) * 3 + (X[:, 1] > 0).astype(int)  # learnable rule
+    c = (X[:, 2] > 0.5).astype(int) * 5
+    w = np.ones(B)
+    theta = mlp.init(3)
+    Xd, ad, cd, wd = dev32(X), dev32(a, torch.int32), dev32(c, torch.int32), dev32(w)
+    th = dev32(theta)
+    m = torch.zeros_like(th)
+    v = torch.zeros_like(th)
+    L_first = None
+    for step in range(1, 301):
+        loss, grad = neig.mlp_grad(Xd, ad, cd, wd, th)
+        if L_first is None:
+            L_first = float(loss.item())
+        neig.mlp_adam(th, grad, m, v, step, 3e-3)
+    L_last = float(neig.mlp_grad(Xd, ad, cd, wd, th)[0].item())
+    say(f"training loss {L_first:.3f} -> {L_last:.3f}")
+    assert L_last < 0.25 * L_first
+    # the oracle agrees on the trained parameters' loss
+    assert abs(mlp.loss(th.cpu().numpy().astype(np.float64), X.astype(np.float32), a, c, w) - L_last) < 1e-3
+
+
+@pytest.mark.parametrize("B", [1, 5, 333])
+def test_bf16_inference_against_oracle(neig, B):
+    import torch
+
+    theta, X, _, _, _ = batch_case(B, 20 + B)
+    z0, _ = mlp.forward(theta.astype(np.float32).astype(np.float64), X.astype(np.float32).astype(np.float64))
+    logits, bins, conf = neig.mlp_infer(dev32(X), dev32(theta))
+    torch.cuda.synchronize()
+    z1 = logits.cpu().numpy().astype(np.float64)
+    scale = np.max(np.abs(z0), axis=1, keepdims=True) + 1.0
+    err = np.abs(z1 - z0) / scale
+    say(f"B={B} max scaled logit error {err.max():.2e}")
+    assert err.max() <= 4e-2  # BF16 operands: 8 significant bits per layer input and weight
+    b1 = bins.cpu().numpy()
+    for h in range(2):
+        zz = z0[:, 8 * h: 8 * h + 8]
+        top2 = np.sort(zz, axis=1)[:, -2:]
+        clear = (top2[:, 1] - top2[:, 0]) > 0.2 * scale[:, 0]
+        assert np.all(b1[clear, h] == np.argmax(zz, axis=1)[clear])
+        p = mlp.softmax(zz)
+        assert np.allclose(conf.cpu().numpy()[clear, h], p[clear].max(axis=1), atol=0.05)
+
+
+@pytest.mark.parametrize("case", ["random", "graded", "small_block"])
+def test_feature_kernel_against_oracle(neig, case):
+    n = 1500 if case != "small_block" else 60
+    g = inputs.rng(inputs.LEARNED, 10 + len(case))
+    H = inputs.graded_hessenberg(n, g) if case == "graded" else inputs.random_hessenberg(n, g)
+    ktop, kbot = (0, n - 1) if case != "random" else (100, n - 7)
+    hnorm = float(np.linalg.norm(H))
+    extra = np.array([0.5, -1.25, 0.3, 0.125], dtype=np.float32)
+    f1, bins, conf = neig.policy_features(to_dev(H), ktop, kbot, hnorm, extra)
+    f0 = mlp.features(H, ktop, kbot, hnorm, extra)
+    say(f"{case}: max feature difference {np.max(np.abs(f1 - f0)):.2e}")
+    assert np.allclose(f1, f0, rtol=1e-5, atol=1e-4)
+    assert np.all(np.diff(f1[1:20]) >= 0)
+
+
+def _solve_and_check(neig, H, tag):
+    Hd = to_dev(H)
+    r = neig.schur(Hd)
+    assert r.info == 0, tag
+    S, Z = to_host(Hd), to_host(r.Z)
+    n = H.shape[0]
+    assert backward_error(H, S, Z) <= 50 * n * EPS, tag
+    assert orthogonality(Z) <= 50 * n * EPS, tag
+    assert structure_violations(S, r.wr.cpu().numpy(), r.wi.cpu().numpy()) == [], tag
+
+
+def test_exploration_runs_are_valid_and_logged(neig):
+    H = inputs.random_hessenberg(700, inputs.rng(inputs.LEARNED, 1))
+    neig.set_params(policy=2, seed=5)
+    try:
+        _solve_and_check(neig, H, "explore")
+        feat, bins, st = neig.policy_log()
+    finally:
+        neig.set_params(policy=0)
+    say(f"explore: {len(bins)} decisions")
+    assert len(bins) > 0
+    assert np.all((bins >= 0) & (bins < 8))
+    assert np.all(st[:, 3] == 1.0) and np.all(st[:, 1] > 0)
+    assert np.all(np.abs(feat[:, 0] - np.log(st[:, 2])) < 1e-5)
+
+
+def test_network_proposals_are_valid(neig):
+    """An untrained network's proposals (any bins) still give a correct Schur
+    form; with min_conf = 1 every decision falls back to the default rules."""
+    theta = mlp.init(9)
+    H = inputs.random_hessenberg(500, inputs.rng(inputs.LEARNED, 2))
+    neig.policy_set(theta.astype(np.float32), 0.0)
+    neig.set_params(policy=1)
+    try:
+        _solve_and_check(neig, H, "learned")
+        st = neig.get_stats()
+        assert st["policy_used"] > 0 and st["policy_fallback"] == 0
+        neig.policy_set(theta.astype(np.float32), 1.0)
+        _solve_and_check(neig, H, "fallback")
+        st = neig.get_stats()
+        assert st["policy_used"] == 0 and st["policy_fallback"] > 0
+    finally:
+        neig.set_params(policy=0)
+        neig.policy_set(None)
