@@ -108,8 +108,7 @@ class Bench:
 
 
 def _set_all(binding, p):
-    k = 6
-    binding.set_batched_tune([1 << 30] * k, [p["nw"]] * k, [p["ns"]] * k, [p["nmin"]] * k, [p["chase_w"]] * k)
+    binding.set_batched_tune([1 << 30], [p["nw"]], [p["ns"]], [p["nmin"]], [p["chase_w"]])
 
 
 def tune_class(lo: int, hi: int, start: dict, count: int, passes: int = 2, log=print):

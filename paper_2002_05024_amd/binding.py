@@ -95,6 +95,9 @@ def load_library():
         return _lib
     if not os.path.exists(_LIB_PATH):
         raise NeigError(f"{_LIB_PATH} is not built (run __graft_entry__.build())")
+    # torch first: the library then binds to the HIP runtime torch has loaded,
+    # so both share one runtime (devices, streams, memory) in this process
+    _torch()
     lib = ctypes.CDLL(_LIB_PATH)
     lib.neig_schur.argtypes = [_i, _vp, _i, _vp, _i, _vp, _vp, _vp]
     lib.neig_schur.restype = _i

@@ -164,13 +164,15 @@ extern "C" __global__ void k_mlp_reduce(const float *partial, const float *loss_
 
 // Adam: m <- b1 m + (1-b1) g; v <- b2 v + (1-b2) g^2;
 // theta <- theta - lr (m / bc1) / (sqrt(v / bc2) + eps); mu and sd untouched.
+// 1 - b1 and 1 - b2 come from the host (in float, 1 - 0.999f loses four digits).
 extern "C" __global__ void k_mlp_adam(float *theta, const float *grad, float *m, float *v, float lr, float beta1,
-                                      float beta2, float eps, float bc1, float bc2) {
+                                      float beta2, float one_m_beta1, float one_m_beta2, float eps, float bc1,
+                                      float bc2) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i < MLP_O_W1 || i >= MLP_NPARAM) return;
     const float gi = grad[i];
-    const float mi = beta1 * m[i] + (1.0f - beta1) * gi;
-    const float vi = beta2 * v[i] + (1.0f - beta2) * gi * gi;
+    const float mi = beta1 * m[i] + one_m_beta1 * gi;
+    const float vi = beta2 * v[i] + one_m_beta2 * gi * gi;
     m[i] = mi;
     v[i] = vi;
     theta[i] -= lr * (mi / bc1) / (sqrtf(vi / bc2) + eps);

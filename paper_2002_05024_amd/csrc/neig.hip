@@ -1140,7 +1140,7 @@ extern "C" int neig_mlp_adam(float *theta, const float *grad, float *m, float *v
     const double b1 = 0.9, b2 = 0.999;
     const float bc1 = (float)(1.0 - std::pow(b1, step)), bc2 = (float)(1.0 - std::pow(b2, step));
     hipLaunchKernelGGL(k_mlp_adam, dim3((MLP_NPARAM + 255) / 256), dim3(256), 0, stream, theta, grad, m, v, lr,
-                       (float)b1, (float)b2, 1e-8f, bc1, bc2);
+                       (float)b1, (float)b2, (float)(1.0 - b1), (float)(1.0 - b2), 1e-8f, bc1, bc2);
     const hipError_t e = hipGetLastError();
     return e == hipSuccess ? 0 : -100 - (int)e;
 }

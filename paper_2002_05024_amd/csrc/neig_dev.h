@@ -26,6 +26,33 @@ struct Refl {
     double tau, v1, v2, beta;
 };
 
+// Square root and reciprocal of an argument well inside the normal range
+// (1e-300 .. 1e300): the hardware approximations refined by Newton steps
+// (Goldschmidt's coupled iteration for the square root), correct to about one
+// unit in the last place.  They skip the range scaling that the general library
+// routines add, which sits on the critical path of every bulge step.
+__device__ __forceinline__ double sqrt_normal(double a) {
+    const double y = __builtin_amdgcn_rsq(a);
+    double g = a * y, h = 0.5 * y;
+    const double r = fma(-g, h, 0.5);
+    g = fma(g, r, g);
+    h = fma(h, r, h);
+    double d = fma(-g, g, a);
+    g = fma(d, h, g);
+    d = fma(-g, g, a);
+    return fma(d, h, g);
+}
+
+__device__ __forceinline__ double rcp_normal(double a) {
+    double y = __builtin_amdgcn_rcp(a);
+    double e = fma(-a, y, 1.0);
+    y = fma(y, e, y);
+    e = fma(-a, y, 1.0);
+    y = fma(y, e, y);
+    e = fma(-a, y, 1.0);
+    return fma(y, e, y);
+}
+
 __device__ __forceinline__ Refl make_refl(double x0, double x1, double x2) {
     Refl r;
     const double s = fabs(x1) + fabs(x2);
@@ -37,10 +64,10 @@ __device__ __forceinline__ Refl make_refl(double x0, double x1, double x2) {
     if (mx > 1e-150 && mx < 1e150) {
         // no overflow or harmful underflow in the squares or in beta (x0 - beta);
         // one division gives both 1/beta and 1/(x0 - beta)
-        const double nrm = sqrt(x0 * x0 + x1 * x1 + x2 * x2);
+        const double nrm = sqrt_normal(x0 * x0 + x1 * x1 + x2 * x2);
         const double beta = (x0 >= 0.0) ? -nrm : nrm;
         const double d = x0 - beta;
-        const double q = 1.0 / (beta * d);
+        const double q = rcp_normal(beta * d);
         const double inv = beta * q;  // 1 / (x0 - beta)
         r.tau = -d * d * q;           // (beta - x0) / beta
         r.v1 = x1 * inv;

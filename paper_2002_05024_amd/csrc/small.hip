@@ -32,7 +32,9 @@
 __shared__ long long g_prof[8];
 #define PROF_T(v) const long long v = clock64()
 #define PROF_ADD(slot, t0) do { if (threadIdx.x == 0) g_prof[slot] += clock64() - (t0); } while (0)
+#define PROF_CNT(slot, v) do { if (threadIdx.x == 0) g_prof[slot] += (v); } while (0)
 #else
+#define PROF_CNT(slot, v) do { } while (0)
 #define PROF_T(v)
 #define PROF_ADD(slot, t0) do { } while (0)
 #endif
@@ -151,81 +153,80 @@ __device__ __forceinline__ void far_apply(double *T, int ldt, double *Q, int ldq
     }
 }
 
-// One bulge step of near_steps for a fixed shape: M3 rows in the reflector and
-// RB = rmax - k + 1 rows in the mixed block (4: interior, 3: second to last,
-// 2: last step).  Every load is unconditional for the lane's role.
-template <int M3, int RB>
-__device__ __forceinline__ void near_step(double *T, int ldt, int l, int k, int k0, int cnear, double *rt, double *r1,
-                                          double *r2, double &x0, double &x1, double &x2) {
+// One bulge step of near_steps, reflector on rows/columns k..k+M3-1 (M3 = 3, or
+// 2 at the last step).  Every lane of wave 0 runs the same instructions on a
+// 3-vector of its own:
+//   lane c (0..31)   column k-1+c, rows k..k+M3-1: c = 0 receives (beta, 0, 0);
+//                    columns k+M3..cnear take the left reflection;
+//   lane 32+t        row k0+t <= min(k+3, i), columns k..k+M3-1: rows k..k+M3-1
+//                    first take the left reflection of their entries (from the
+//                    column sums of the M3 x M3 diagonal block, which every
+//                    lane reads), then every row takes the right reflection.
+// Only the stores are predicated.  The generating vector of step k+1 (column k,
+// rows k+1..k+3) is read from the row lanes with readlane.
+template <int M3>
+__device__ __forceinline__ void near_step(double *T, int ldt, int l, int i, int k, int k0, int cnear, double *rt,
+                                          double *r1, double *r2, double &x0, double &x1, double &x2) {
     const int lane = threadIdx.x;
-    double blk[RB][M3];
-    double o[M3];
-    int cj = 0, rr = 0;
-    const bool isM = (lane == 0);
-    const bool isL = (lane >= 1 && lane < 32) && (k + M3 - 1 + lane <= cnear);
-    const bool isR = (lane >= 32) && (k0 + lane - 32 < k);
-    if (isM) {
+    const int rmax = (k + 3 < i) ? k + 3 : i;
+    const bool isRow = lane >= 32;
+    const int col = k - 1 + lane;                 // column lanes
+    const int row = k0 + lane - 32;               // row lanes
+    const bool colOn = !isRow && lane > M3 && col <= cnear;
+    const bool betaOn = (lane == 0) && (k > l);
+    const bool rowOn = isRow && row <= rmax;
+    double *vec = colOn ? &AT(T, ldt, k, col) : (rowOn ? &AT(T, ldt, row, k) : T);
+    const int vs = colOn ? 1 : (rowOn ? ldt : 0);
+    double v[3];
 #pragma unroll
-        for (int a = 0; a < RB; ++a)
+    for (int a = 0; a < M3; ++a) v[a] = vec[a * vs];
+    double blk[M3][M3];  // the diagonal block, same addresses for every lane
 #pragma unroll
-            for (int b = 0; b < M3; ++b) blk[a][b] = AT(T, ldt, k + a, k + b);
-    } else if (isL) {
-        cj = k + M3 - 1 + lane;
+    for (int a = 0; a < M3; ++a)
 #pragma unroll
-        for (int a = 0; a < M3; ++a) o[a] = AT(T, ldt, k + a, cj);
-    } else if (isR) {
-        rr = k0 + lane - 32;
+        for (int b = 0; b < M3; ++b) blk[a][b] = AT(T, ldt, k + a, k + b);
+    const Refl r = make_refl(x0, x1, (M3 == 3) ? x2 : 0.0);
+    const double w1 = r.v1, w2 = (M3 == 3) ? r.v2 : 0.0;
+    // left reflection of a row lane's entries in rows k..k+M3-1
+    const int q = row - k;
+    const double lw = (rowOn && q >= 0 && q < M3) ? r.tau * (q == 0 ? 1.0 : (q == 1 ? w1 : w2)) : 0.0;
 #pragma unroll
-        for (int b = 0; b < M3; ++b) o[b] = AT(T, ldt, rr, k + b);
+    for (int b = 0; b < M3; ++b) {
+        double sc = blk[0][b] + w1 * blk[1][b];
+        if (M3 == 3) sc += w2 * blk[2][b];
+        v[b] -= lw * sc;
     }
-    Refl r = make_refl(x0, x1, (M3 == 3) ? x2 : 0.0);
-    const double v2 = (M3 == 3) ? r.v2 : 0.0;
-    double n0 = 0.0, n1 = 0.0, n2 = 0.0;
-    if (isM) {
+    // the step's own reflection: left for column lanes, right for row lanes
+    double s = v[0] + w1 * v[1];
+    if (M3 == 3) s += w2 * v[2];
+    s *= r.tau;
+    v[0] -= s;
+    v[1] -= s * w1;
+    if (M3 == 3) v[2] -= s * w2;
+    if (colOn || rowOn) {
+#pragma unroll
+        for (int a = 0; a < M3; ++a) vec[a * vs] = v[a];
+    }
+    if (betaOn) {
+        AT(T, ldt, k, k - 1) = r.beta;
+        AT(T, ldt, k + 1, k - 1) = 0.0;
+        if (M3 == 3) AT(T, ldt, k + 2, k - 1) = 0.0;
+    }
+    if (lane == 0) {
         rt[k - k0] = r.tau;
-        r1[k - k0] = r.v1;
-        r2[k - k0] = v2;
-#pragma unroll
-        for (int b = 0; b < M3; ++b) {
-            double c = (M3 == 3) ? blk[2][b] : 0.0;
-            refl_apply3(blk[0][b], blk[1][b], c, r.tau, r.v1, v2);
-            if (M3 == 3) blk[2][b] = c;
-        }
-#pragma unroll
-        for (int a = 0; a < RB; ++a) {
-            double c = (M3 == 3) ? blk[a][2] : 0.0;
-            refl_apply3(blk[a][0], blk[a][1], c, r.tau, r.v1, v2);
-            if (M3 == 3) blk[a][2] = c;
-        }
-#pragma unroll
-        for (int a = 0; a < RB; ++a)
-#pragma unroll
-            for (int b = 0; b < M3; ++b) AT(T, ldt, k + a, k + b) = blk[a][b];
-        if (k > l) {
-            AT(T, ldt, k, k - 1) = r.beta;
-            AT(T, ldt, k + 1, k - 1) = 0.0;
-            if (M3 == 3) AT(T, ldt, k + 2, k - 1) = 0.0;
-        }
-        if (RB > 1) n0 = blk[1][0];
-        if (RB > 2) n1 = blk[2][0];
-        if (RB > 3) n2 = blk[3][0];
-    } else if (isL) {
-        double c = (M3 == 3) ? o[M3 - 1] : 0.0;
-        refl_apply3(o[0], o[1], c, r.tau, r.v1, v2);
-        AT(T, ldt, k, cj) = o[0];
-        AT(T, ldt, k + 1, cj) = o[1];
-        if (M3 == 3) AT(T, ldt, k + 2, cj) = c;
-    } else if (isR) {
-        double c = (M3 == 3) ? o[M3 - 1] : 0.0;
-        refl_apply3(o[0], o[1], c, r.tau, r.v1, v2);
-        AT(T, ldt, rr, k) = o[0];
-        AT(T, ldt, rr, k + 1) = o[1];
-        if (M3 == 3) AT(T, ldt, rr, k + 2) = c;
+        r1[k - k0] = w1;
+        r2[k - k0] = w2;
     }
-    // generating vector of step k+1: column k, rows k+1..k+3 (lane 0's block)
-    x0 = bcast_lane0(n0);
-    x1 = bcast_lane0(n1);
-    x2 = bcast_lane0(n2);
+    // generating vector of step k+1: column k, rows k+1..k+3
+    const int lb = 32 + (k + 1 - k0);
+    x0 = __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(v[0]), lb),
+                          __builtin_amdgcn_readlane(__double2loint(v[0]), lb));
+    x1 = (k + 2 <= rmax) ? __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(v[0]), lb + 1),
+                                            __builtin_amdgcn_readlane(__double2loint(v[0]), lb + 1))
+                         : 0.0;
+    x2 = (k + 3 <= rmax) ? __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(v[0]), lb + 2),
+                                            __builtin_amdgcn_readlane(__double2loint(v[0]), lb + 2))
+                         : 0.0;
 }
 
 // Wave 0: bulge steps k0..k1-1 of the double-shift sweep on rows/cols l..i with
@@ -249,12 +250,10 @@ __device__ __forceinline__ void near_steps(double *T, int ldt, int l, int i, int
             x1 = c * (a + d - t);
             x2 = c * e;
         }
-        if (k + 3 <= i)
-            near_step<3, 4>(T, ldt, l, k, k0, cnear, rt, r1, r2, x0, x1, x2);
-        else if (k + 2 == i)
-            near_step<3, 3>(T, ldt, l, k, k0, cnear, rt, r1, r2, x0, x1, x2);
+        if (k + 2 <= i)
+            near_step<3>(T, ldt, l, i, k, k0, cnear, rt, r1, r2, x0, x1, x2);
         else
-            near_step<2, 2>(T, ldt, l, k, k0, cnear, rt, r1, r2, x0, x1, x2);
+            near_step<2>(T, ldt, l, i, k, k0, cnear, rt, r1, r2, x0, x1, x2);
     }
 }
 
@@ -263,6 +262,7 @@ __device__ __forceinline__ void near_steps(double *T, int ldt, int l, int i, int
 __device__ __forceinline__ void lds_francis(double *T, int ldt, double *Q, int ldq, int m, int l, int i, double tr, double det) {
     __shared__ double rq[2][3][FB];
     const int tid = threadIdx.x, wave = tid / LANES;
+    PROF_CNT(4, i - l);
     double x0 = 0.0, x1 = 0.0, x2 = 0.0;
     int pk0 = -1, pnb = 0, pcnear = 0, pb = 0, cb = 0;
     for (int k0 = l; k0 <= i - 1; k0 += FB) {

@@ -142,9 +142,17 @@ def collect(start: int, count: int, out: str, lo: int, hi: int, seed: int, threa
         runs.append(np.full(len(b), i, dtype=np.int32))
         log(f"[collect] {i} {fam} n={H.shape[0]} {sec:.2f}s info={info} decisions={len(b)} "
             f"elapsed {time.time() - t0:.0f}s")
+        if len(runs) % 25 == 0:  # keep what is done if the run is cut short
+            _save(out, feats, bins, stats, runs)
     binding.set_params(policy=0)
-    np.savez_compressed(out, feat=np.concatenate(feats), bins=np.concatenate(bins), stats=np.concatenate(stats),
+    _save(out, feats, bins, stats, runs)
+
+
+def _save(out, feats, bins, stats, runs):
+    tmp = out + ".tmp.npz"
+    np.savez_compressed(tmp, feat=np.concatenate(feats), bins=np.concatenate(bins), stats=np.concatenate(stats),
                         run=np.concatenate(runs))
+    os.replace(tmp, out)
 
 
 def sample_weights(stats, run, beta: float = 1.5):
