@@ -8,10 +8,11 @@
 //
 // One launch carries several strips ("tasks"); each workgroup owns a 64-wide
 // slice of one strip (64 columns for side 0, 64 rows for side 1), reads all of
-// it before writing, so in-place is safe.  Four waves; each wave owns one
-// 16-wide column (side 0) or row (side 1) tile of the slice and loops over all
-// of the window's 16-row tiles, so the U^T operand streams from L2 while the
-// strip operand comes from LDS (side 0) or straight from HBM (side 1).
+// it before writing, so in-place is safe.  U^T is staged in LDS once per
+// workgroup.  Four waves; each wave owns one 16-wide column (side 0) or row
+// (side 1) tile of the slice and loops over all of the window's 16-row tiles;
+// the strip operand comes from LDS (side 0) or from registers loaded all at
+// once at the start (side 1).
 //
 // Operand layouts of v_mfma_f64_16x16x4_f64 (lane l, 64 lanes): A(16x4) element
 // (l%16, l/16); B(4x16) element (l/16, l%16); the four accumulator doubles of
@@ -40,7 +41,7 @@ __device__ __forceinline__ neig_d4 mfma16(double a, double b, neig_d4 c) {
 
 extern "C" __global__ void __launch_bounds__(UPD_THREADS)
 k_update(UpdArgs args) {
-    extern __shared__ double Cs[];
+    extern __shared__ double lds[];
     int ti = 0;
     const int bid = blockIdx.x;
     while (ti + 1 < args.ntask && args.t[ti + 1].tile0 <= bid) ++ti;
@@ -53,6 +54,9 @@ k_update(UpdArgs args) {
     const int kp = (w + 3) & ~3;
     const int nrt = wp >> 4;
     const int li = lane & 15, lk = lane >> 4;
+    const int ldus = wp + 1;
+    double *Us = lds;                       // U^T, wp x wp (zero padded), leading dimension ldus
+    double *Cs = lds + (size_t)wp * ldus;   // side 0: the strip's slice
     neig_d4 acc[8];
 #pragma unroll
     for (int r = 0; r < 8; ++r) acc[r] = (neig_d4){0.0, 0.0, 0.0, 0.0};
@@ -66,6 +70,10 @@ k_update(UpdArgs args) {
             if (r < w && c0 + c < T.len) v = AT(T.C, T.ldc, r, c0 + c);
             Cs[r + c * ldcs] = v;
         }
+        for (int idx = threadIdx.x; idx < wp * wp; idx += UPD_THREADS) {
+            const int r = idx % wp, k = idx / wp;
+            Us[r + k * ldus] = (r < w && k < w) ? AT(T.Ut, T.ldu, r, k) : 0.0;
+        }
         __syncthreads();
         const int cb = 16 * q + li;
         for (int k = 0; k < kp; k += 4) {
@@ -73,11 +81,7 @@ k_update(UpdArgs args) {
             const double b = Cs[kk + cb * ldcs];
 #pragma unroll
             for (int rt = 0; rt < 8; ++rt) {
-                if (rt < nrt) {
-                    const int ar = 16 * rt + li;
-                    const double a = (ar < w && kk < w) ? AT(T.Ut, T.ldu, ar, kk) : 0.0;
-                    acc[rt] = mfma16(a, b, acc[rt]);
-                }
+                if (rt < nrt) acc[rt] = mfma16(Us[(16 * rt + li) + kk * ldus], b, acc[rt]);
             }
         }
         const int col = c0 + 16 * q + li;
@@ -94,17 +98,28 @@ k_update(UpdArgs args) {
             }
         }
     } else {
+        // the wave's 16 rows of the strip, every k at once (all loads in flight
+        // together), then U^T from LDS
         const int rbase = tile * UPD_SLICE + 16 * q;
         const int arow = rbase + li;
-        for (int k = 0; k < kp; k += 4) {
-            const int kk = k + lk;
-            const double a = (arow < T.len && kk < w) ? AT(T.C, T.ldc, arow, kk) : 0.0;
+        double areg[UPD_WMAX / 4];
 #pragma unroll
-            for (int ct = 0; ct < 8; ++ct) {
-                if (ct < nrt) {
-                    const int bc = 16 * ct + li;
-                    const double b = (bc < w && kk < w) ? AT(T.Ut, T.ldu, bc, kk) : 0.0;
-                    acc[ct] = mfma16(a, b, acc[ct]);
+        for (int s4 = 0; s4 < UPD_WMAX / 4; ++s4) {
+            const int kk = 4 * s4 + lk;
+            areg[s4] = (4 * s4 < kp && arow < T.len && kk < w) ? AT(T.C, T.ldc, arow, kk) : 0.0;
+        }
+        for (int idx = threadIdx.x; idx < wp * wp; idx += UPD_THREADS) {
+            const int r = idx % wp, k = idx / wp;
+            Us[r + k * ldus] = (r < w && k < w) ? AT(T.Ut, T.ldu, r, k) : 0.0;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int s4 = 0; s4 < UPD_WMAX / 4; ++s4) {
+            if (4 * s4 < kp) {
+                const int kk = 4 * s4 + lk;
+#pragma unroll
+                for (int ct = 0; ct < 8; ++ct) {
+                    if (ct < nrt) acc[ct] = mfma16(areg[s4], Us[(16 * ct + li) + kk * ldus], acc[ct]);
                 }
             }
         }

@@ -325,7 +325,8 @@ class Solver {
             }
             a.ntask = nt;
             if (nt == 0 || tiles == 0) continue;
-            size_t lds = any_left ? (size_t)(wmaxp + 1) * UPD_SLICE * sizeof(double) : 0;
+            size_t lds = (size_t)wmaxp * (wmaxp + 1) * sizeof(double);  // U^T
+            if (any_left) lds += (size_t)(wmaxp + 1) * UPD_SLICE * sizeof(double);
             timed(kUpdate, [&] {
                 hipLaunchKernelGGL(k_update, dim3(tiles), dim3(UPD_THREADS), lds, st_, a);
                 ck(hipGetLastError());

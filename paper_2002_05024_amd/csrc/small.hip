@@ -153,17 +153,19 @@ __device__ __forceinline__ void far_apply(double *T, int ldt, double *Q, int ldq
     }
 }
 
-// One bulge step of near_steps, reflector on rows/columns k..k+M3-1 (M3 = 3, or
-// 2 at the last step).  Every lane of wave 0 runs the same instructions on a
-// 3-vector of its own:
-//   lane c (0..31)   column k-1+c, rows k..k+M3-1: c = 0 receives (beta, 0, 0);
-//                    columns k+M3..cnear take the left reflection;
+// One bulge step, reflector on rows/columns k..k+M3-1 (M3 = 3, or 2 at the last
+// step of a sweep), generated from (x0, x1, x2), recorded for the far field and
+// applied to the near field.  Every lane of wave 0 runs the same instructions on
+// a 3-vector of its own:
+//   lane c (0..31)   column k-1+c, rows k..k+M3-1: c = 0 receives (beta, 0, 0)
+//                    when k > l; columns k+M3..cnear take the left reflection;
 //   lane 32+t        row k0+t <= min(k+3, i), columns k..k+M3-1: rows k..k+M3-1
 //                    first take the left reflection of their entries (from the
 //                    column sums of the M3 x M3 diagonal block, which every
 //                    lane reads), then every row takes the right reflection.
-// Only the stores are predicated.  The generating vector of step k+1 (column k,
-// rows k+1..k+3) is read from the row lanes with readlane.
+// The loads come first so that their latency hides behind the reflector's
+// dependent chain; only the stores are predicated.  The next generating vector
+// (column k, rows k+1..k+3) comes back from the row lanes through readlane.
 template <int M3>
 __device__ __forceinline__ void near_step(double *T, int ldt, int l, int i, int k, int k0, int cnear, double *rt,
                                           double *r1, double *r2, double &x0, double &x1, double &x2) {
@@ -185,7 +187,7 @@ __device__ __forceinline__ void near_step(double *T, int ldt, int l, int i, int 
     for (int a = 0; a < M3; ++a)
 #pragma unroll
         for (int b = 0; b < M3; ++b) blk[a][b] = AT(T, ldt, k + a, k + b);
-    const Refl r = make_refl(x0, x1, (M3 == 3) ? x2 : 0.0);
+    Refl r = make_refl(x0, x1, (M3 == 3) ? x2 : 0.0);
     const double w1 = r.v1, w2 = (M3 == 3) ? r.v2 : 0.0;
     // left reflection of a row lane's entries in rows k..k+M3-1
     const int q = row - k;
@@ -217,7 +219,6 @@ __device__ __forceinline__ void near_step(double *T, int ldt, int l, int i, int 
         r1[k - k0] = w1;
         r2[k - k0] = w2;
     }
-    // generating vector of step k+1: column k, rows k+1..k+3
     const int lb = 32 + (k + 1 - k0);
     x0 = __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(v[0]), lb),
                           __builtin_amdgcn_readlane(__double2loint(v[0]), lb));
@@ -428,6 +429,7 @@ __device__ __forceinline__ bool solve_cp(double (&M)[K][K], double (&r)[K], doub
         for (int j = 0; j < K; ++j) mx = fmax(mx, fabs(M[i][j]));
     }
     const double smin = fmax(NEIG_EPS * mx, NEIG_DBL_MIN);
+    double rinv[K];
 #pragma unroll
     for (int s = 0; s < K; ++s) {
         int pr = s, pc = s;
@@ -466,9 +468,11 @@ __device__ __forceinline__ bool solve_cp(double (&M)[K][K], double (&r)[K], doub
             perm[j] = sw ? pa : pb;
         }
         if (fabs(M[s][s]) < smin) M[s][s] = smin;
+        const double inv = 1.0 / M[s][s];
+        rinv[s] = inv;
 #pragma unroll
         for (int i = s + 1; i < K; ++i) {
-            const double f = M[i][s] / M[s][s];
+            const double f = M[i][s] * inv;
 #pragma unroll
             for (int j = s; j < K; ++j) M[i][j] -= f * M[s][j];
             r[i] -= f * r[s];
@@ -480,7 +484,7 @@ __device__ __forceinline__ bool solve_cp(double (&M)[K][K], double (&r)[K], doub
         double t = r[s];
 #pragma unroll
         for (int j = s + 1; j < K; ++j) t -= M[s][j] * y[j];
-        y[s] = t / M[s][s];
+        y[s] = t * rinv[s];
     }
     bool ok = true;
 #pragma unroll
@@ -564,14 +568,17 @@ __device__ __forceinline__ bool swap_transform(const double (&B)[P + Q][P + Q], 
             for (int t = c + 1; t < N; ++t) mx = fmax(mx, fabs(v[t]));
             if (mx == 0.0) continue;
             const double sc = fmax(mx, fabs(v[c]));
+            const double rsc = 1.0 / sc;
             double ss = 0.0;
 #pragma unroll
-            for (int t = c; t < N; ++t) ss += (v[t] / sc) * (v[t] / sc);
+            for (int t = c; t < N; ++t) ss += (v[t] * rsc) * (v[t] * rsc);
             const double nrm = sc * sqrt(ss);
             const double alpha = v[c];
             const double beta = alpha >= 0.0 ? -nrm : nrm;
-            const double tau = (beta - alpha) / beta;
-            const double inv = 1.0 / (alpha - beta);
+            const double dd = alpha - beta;
+            const double qq = 1.0 / (beta * dd);  // one division for 1/beta and 1/(alpha - beta)
+            const double tau = -dd * dd * qq;     // (beta - alpha) / beta
+            const double inv = beta * qq;         // 1 / (alpha - beta)
 #pragma unroll
             for (int t = c + 1; t < N; ++t) v[t] *= inv;
             v[c] = 1.0;
@@ -594,6 +601,8 @@ __device__ __forceinline__ bool swap_transform(const double (&B)[P + Q][P + Q], 
                 for (int t = c; t < N; ++t) Qm[i][t] -= d * v[t];
             }
         }
+        // Bn = Qm^T (B Qm); B is block upper triangular (rows P.. are zero in
+        // columns ..P-1)
         double W[N][N];
 #pragma unroll
         for (int i = 0; i < N; ++i)
@@ -601,7 +610,7 @@ __device__ __forceinline__ bool swap_transform(const double (&B)[P + Q][P + Q], 
             for (int j = 0; j < N; ++j) {
                 double d = 0.0;
 #pragma unroll
-                for (int k = 0; k < N; ++k) d += B[i][k] * Qm[k][j];
+                for (int k = (i < P ? 0 : P); k < N; ++k) d += B[i][k] * Qm[k][j];
                 W[i][j] = d;
             }
 #pragma unroll
@@ -623,14 +632,15 @@ __device__ __forceinline__ bool swap_transform(const double (&B)[P + Q][P + Q], 
                 Bn[i][j] = 0.0;
             }
         if (!(low <= thresh)) return false;
-        // reconstruction: B ~ Qm Bn Qm^T
+        // reconstruction: B ~ Qm Bn Qm^T (Bn now block upper triangular: rows Q..
+        // are zero in columns ..Q-1)
 #pragma unroll
         for (int i = 0; i < N; ++i)
 #pragma unroll
             for (int j = 0; j < N; ++j) {
                 double d = 0.0;
 #pragma unroll
-                for (int k = 0; k < N; ++k) d += Bn[i][k] * Qm[j][k];
+                for (int k = (i < Q ? 0 : Q); k < N; ++k) d += Bn[i][k] * Qm[j][k];
                 W[i][j] = d;
             }
         double err = 0.0;
@@ -699,8 +709,8 @@ __device__ __forceinline__ bool lds_swap_pq(double *T, int ldt, double *V, int l
             for (int j = 0; j < N; ++j) AT(T, ldt, st + i, st + j) = Bn[i][j];
     }
     __syncthreads();
-    if (Q == 2 && AT(T, ldt, st + 1, st) != 0.0) lds_standardise(T, ldt, V, ldv, nw, st);
-    if (P == 2 && AT(T, ldt, st + Q + 1, st + Q) != 0.0) lds_standardise(T, ldt, V, ldv, nw, st + Q);
+    // the 2x2 blocks of Bn are similar to the old ones but not in standard form;
+    // aed_core standardises the deflated ones once, after all swaps
     return true;
 }
 
@@ -708,7 +718,11 @@ __device__ __forceinline__ bool lds_swap(double *T, int ldt, double *V, int ldv,
     if (p == 1 && q == 1) return lds_swap_pq<1, 1>(T, ldt, V, ldv, nw, st);
     if (p == 1 && q == 2) return lds_swap_pq<1, 2>(T, ldt, V, ldv, nw, st);
     if (p == 2 && q == 1) return lds_swap_pq<2, 1>(T, ldt, V, ldv, nw, st);
-    return lds_swap_pq<2, 2>(T, ldt, V, ldv, nw, st);
+    PROF_T(p22);
+    const bool ok = lds_swap_pq<2, 2>(T, ldt, V, ldv, nw, st);
+    PROF_CNT(5, 1);
+    PROF_ADD(6, p22);
+    return ok;
 }
 
 // ---------------------------------------------------------------- Householder helpers (vector in LDS)
@@ -789,6 +803,28 @@ struct AedOut {
 // swaps, undeflated Ritz values written to sr/si (thread 0), and, if anything
 // deflated, the spike and the undeflated part reduced back to Hessenberg form.
 // On return T and V hold the transformed window and its orthogonal factor.
+// Spike test of the diagonal block at j (size bs) of the AED window: the
+// window criterion |s v| <= max(smlnum, eps |lambda|) (criterion 0) or the
+// norm-stable |s v| <= max(smlnum, eps ||H||_F) (criterion 1), v the block's
+// entries in the first row of V.
+__device__ __forceinline__ bool aed_block_deflates(const double *T, const double *V, int ld, double s, int j, int bs,
+                                                   double hnorm, double smlnum, int criterion) {
+    double sp = fabs(s * AT(V, ld, 0, j));
+    if (bs == 2) sp = fmax(sp, fabs(s * AT(V, ld, 0, j + 1)));
+    double tol;
+    if (criterion == 1) {
+        tol = NEIG_EPS * hnorm;
+    } else {
+        double lam = (bs == 1) ? fabs(AT(T, ld, j, j))
+                               : sqrt(fabs(AT(T, ld, j, j) * AT(T, ld, j + 1, j + 1) -
+                                           AT(T, ld, j, j + 1) * AT(T, ld, j + 1, j)));
+        if (lam == 0.0) lam = fabs(s);
+        tol = NEIG_EPS * lam;
+    }
+    tol = fmax(tol, smlnum);
+    return sp <= tol;
+}
+
 __device__ __forceinline__ AedOut aed_core(double *T, double *V, int ld, double *x, int nw, double s, double hnorm, double smlnum,
                            int criterion, int maxit, double *sr, double *si) {
     const int tid = threadIdx.x;
@@ -800,26 +836,14 @@ __device__ __forceinline__ AedOut aed_core(double *T, double *V, int ld, double 
     const long long c1 = clock64();
     o.nswap = 0;
     o.late = 0;
-    int top = o.infqr, kend = nw;
     o.swapfail = 0;
+    int top = o.infqr, kend = nw;
     while (kend > top) {
         const int bs = (kend - 2 >= top && AT(T, ld, kend - 1, kend - 2) != 0.0) ? 2 : 1;
         const int j = kend - bs;
-        double sp = fabs(s * AT(V, ld, 0, j));
-        if (bs == 2) sp = fmax(sp, fabs(s * AT(V, ld, 0, j + 1)));
-        double tol;
-        if (criterion == 1) {
-            tol = NEIG_EPS * hnorm;
-        } else {
-            double lam = (bs == 1) ? fabs(AT(T, ld, j, j))
-                                   : sqrt(fabs(AT(T, ld, j, j) * AT(T, ld, j + 1, j + 1) -
-                                               AT(T, ld, j, j + 1) * AT(T, ld, j + 1, j)));
-            if (lam == 0.0) lam = fabs(s);
-            tol = NEIG_EPS * lam;
-        }
-        tol = fmax(tol, smlnum);
+        const bool defl = aed_block_deflates(T, V, ld, s, j, bs, hnorm, smlnum, criterion);
         __syncthreads();  // all threads have read the test inputs before any swap writes
-        if (sp <= tol) {
+        if (defl) {
             if (top > o.infqr) o.late += bs;
             kend -= bs;
             continue;
@@ -844,6 +868,17 @@ __device__ __forceinline__ AedOut aed_core(double *T, double *V, int ld, double 
         top += bs;
     }
     o.nd = nw - kend;
+    // standard form for the deflated 2x2 blocks (swaps leave them in any form);
+    // a block whose eigenvalues came out real is split into two 1x1 blocks
+    for (int j = kend; j + 1 < nw;) {
+        if (AT(T, ld, j + 1, j) != 0.0) {
+            const double a = AT(T, ld, j, j), b = AT(T, ld, j, j + 1), c = AT(T, ld, j + 1, j), d = AT(T, ld, j + 1, j + 1);
+            if (!(a == d && b * c < 0.0)) lds_standardise(T, ld, V, ld, nw, j);
+            j += 2;
+        } else {
+            ++j;
+        }
+    }
     const long long c2 = clock64();
 
     // undeflated Ritz values (shift candidates), top to bottom

@@ -1,0 +1,78 @@
+"""Host-side logic that needs no GPU: the input generators of the batched and
+learned workloads, the training-weight rule, and the autotuner's candidate
+filter."""
+import numpy as np
+import pytest
+
+from paper_2002_05024_amd import inputs
+
+
+@pytest.mark.parametrize("n", [5, 40, 131])
+def test_prescribed_hessenberg_keeps_the_spectrum(n):
+    H, lam = inputs.prescribed_hessenberg(n, inputs.rng(90, n), 0.1 / np.sqrt(n))
+    assert np.all(np.tril(H, -2) == 0)
+    ev = np.linalg.eigvals(H)
+    # well-conditioned T: the eigenvalues of H are the prescribed ones
+    d = np.abs(np.sort_complex(ev) - np.sort_complex(lam))
+    assert d.max() < 1e-10
+
+
+def test_prescribed_hessenberg_first_column_is_uniform_on_the_sphere():
+    """The construction's first basis vector P e1 = w is uniform: the mean of
+    w over many draws is ~0 and E[w_k^2] = 1/n."""
+    n, draws = 6, 4000
+    ws = []
+    for k in range(draws):
+        g = inputs.rng(91, k)
+        inputs.prescribed_quasi_triangular(n, g, 0.0)  # same draw order as the generator
+        w = g.standard_normal(n)
+        ws.append(w / np.linalg.norm(w))
+    ws = np.array(ws)
+    assert np.all(np.abs(ws.mean(axis=0)) < 0.05)
+    assert np.allclose((ws ** 2).mean(axis=0), 1.0 / n, atol=0.02)
+
+
+def test_batched_workload_sizes_and_families():
+    Hs, lams = inputs.batched_workload(count=12, seed=3, lo=32, hi=64, threads=2)
+    assert len(Hs) == 12
+    for i, (H, lam) in enumerate(zip(Hs, lams)):
+        n = H.shape[0]
+        assert 32 <= n <= 64 and H.flags.f_contiguous
+        assert np.all(np.tril(H, -2) == 0)
+        assert (lam is None) == (i % 2 == 0)
+    # deterministic
+    Hs2, _ = inputs.batched_workload(count=12, seed=3, lo=32, hi=64, threads=3)
+    assert all(np.array_equal(a, b) for a, b in zip(Hs, Hs2))
+
+
+def test_learned_matrices_three_families():
+    from paper_2002_05024_amd import learn
+
+    fams = [learn.make_matrix(i, "train", 60, 80)[0] for i in range(6)]
+    assert fams == ["random", "prescribed", "graded"] * 2
+    fam, H = learn.make_matrix(2, "train", 60, 80)
+    row_scale = np.abs(H).max(axis=1)
+    assert row_scale[-1] < 1e-6 * row_scale[0]  # graded: 10^(-8 i / n)
+    _, H0 = learn.make_matrix(0, "heldout", 60, 80)
+    _, H1 = learn.make_matrix(0, "train", 60, 80)
+    assert not np.array_equal(H0, H1)  # held-out matrices are other draws
+
+
+def test_sample_weights_rule():
+    from paper_2002_05024_amd import learn
+
+    # two runs; rewards = deflations / ms
+    stats = np.array([[10, 1, 100, 1], [20, 1, 100, 1], [30, 1, 100, 1],   # run 0: rewards 10, 20, 30
+                      [5, 1, 90, 1], [5, 1, 90, 1]], dtype=np.float32)      # run 1: all equal
+    run = np.array([0, 0, 0, 1, 1])
+    w = learn.sample_weights(stats, run, beta=1.0)
+    assert w[0] == 0 and w[1] == 0  # at or below the run's median
+    assert w[2] == pytest.approx(np.exp(np.log((30 + 1e-3) / (20 + 1e-3))), rel=1e-6)
+    assert np.all(w[3:] == 0)
+
+
+def test_autotune_candidate_filter():
+    from paper_2002_05024_amd import autotune
+
+    assert autotune._valid({"nw": 64, "ns": 32, "nmin": 96, "chase_w": 50})
+    assert not autotune._valid({"nw": 64, "ns": 32, "nmin": 96, "chase_w": 49})
