@@ -50,6 +50,9 @@ def _load():
     lib.neig_oracle_cond.argtypes = [i, _dp, i, _dp]
     lib.neig_oracle_cond_subset.argtypes = [i, _dp, i, ctypes.POINTER(ctypes.c_int), i, _dp]
     lib.neig_oracle_last_iterations.argtypes = []
+    lib.neig_oracle_swap.argtypes = [i, _dp, i, _dp, i, i, i, i]
+    lib.neig_oracle_reorder.argtypes = [i, _dp, i, _dp, i, ctypes.POINTER(ctypes.c_int), _dp, _dp,
+                                        ctypes.POINTER(ctypes.c_int)]
     _lib = lib
     return lib
 
@@ -142,3 +145,31 @@ def cond_subset(S, idx):
     if info != 0:
         raise ValueError(f"neig_oracle_cond_subset: info={info}")
     return out
+
+
+def swap(S, Z, st: int, p: int, q: int):
+    """Exchange the adjacent diagonal blocks at st (sizes p then q).  Returns
+    (S, Z, info); info 1 = swap rejected."""
+    lib = _load()
+    Sc = _f64(S)
+    Zc = _f64(Z)
+    n = Sc.shape[0]
+    info = lib.neig_oracle_swap(n, _ptr(Sc), max(1, n), _ptr(Zc), max(1, n), int(st), int(p), int(q))
+    return Sc, Zc, info
+
+
+def reorder(S, Z, select):
+    """Move the selected eigenvalues to the leading block (relative order kept).
+    Returns (S, Z, wr, wi, m, info)."""
+    lib = _load()
+    Sc = _f64(S)
+    Zc = _f64(Z)
+    n = Sc.shape[0]
+    sel = np.ascontiguousarray(select, dtype=np.int32)
+    wr = np.zeros(n)
+    wi = np.zeros(n)
+    m = ctypes.c_int()
+    info = lib.neig_oracle_reorder(n, _ptr(Sc), max(1, n), _ptr(Zc), max(1, n),
+                                   sel.ctypes.data_as(ctypes.POINTER(ctypes.c_int)), _ptr(wr), _ptr(wi),
+                                   ctypes.byref(m))
+    return Sc, Zc, wr, wi, m.value, info

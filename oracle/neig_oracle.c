@@ -24,6 +24,11 @@
  *   neig_oracle_cond        eigenvalue condition numbers |x| |y| / |y^H x| of a
  *                           quasi-triangular S from its left and right
  *                           eigenvectors (substitution).
+ *   neig_oracle_swap        exchange of two adjacent diagonal blocks (Bai and
+ *                           Demmel's Sylvester-equation construction, which
+ *                           the paper cites for its reordering phase).
+ *   neig_oracle_reorder     selected eigenvalues moved to the leading block by
+ *                           adjacent swaps, in order.
  *
  * Readings where the paper is silent (listed again in the design notes):
  *   - negligible subdiagonal: |h(k,k-1)| <= max(smlnum, eps(|h(k-1,k-1)|+|h(k,k)|)),
@@ -493,3 +498,264 @@ int neig_oracle_cond_subset(int n, const double *S, int lds, const int *idx, int
     return rc;
 }
 
+
+/* ------------------------------------------------------------------------
+ * Eigenvalue reordering (the reordering phase the paper runs after the Schur
+ * reduction: an orthogonal similarity that moves chosen eigenvalues to the
+ * leading diagonal block).  Adjacent diagonal blocks A (p x p) and C (q x q)
+ * with coupling B are exchanged by the construction the paper cites (Bai and
+ * Demmel): solve the Sylvester equation A X - X C = B, take Q from the QR
+ * factorisation of [-X; I] (its first q columns span the invariant subspace of
+ * C), and apply Q^T (.) Q.  The lower-left block of the result is set to zero;
+ * the swap is rejected when that block or the reconstruction error exceeds
+ * 20 eps ||block||.
+ * ---------------------------------------------------------------------- */
+
+/* Solve the k x k system M y = r (k <= 4) by Gaussian elimination with partial
+ * pivoting; M and r are overwritten.  Returns 0, or 1 for a zero pivot. */
+static int solve_small(int k, double M[4][4], double r[4]) {
+    for (int s = 0; s < k; ++s) {
+        int piv = s;
+        for (int i = s + 1; i < k; ++i)
+            if (fabs(M[i][s]) > fabs(M[piv][s])) piv = i;
+        if (M[piv][s] == 0.0) return 1;
+        for (int j = 0; j < k; ++j) {
+            double t = M[s][j]; M[s][j] = M[piv][j]; M[piv][j] = t;
+        }
+        double t = r[s]; r[s] = r[piv]; r[piv] = t;
+        for (int i = s + 1; i < k; ++i) {
+            const double f = M[i][s] / M[s][s];
+            for (int j = s; j < k; ++j) M[i][j] -= f * M[s][j];
+            r[i] -= f * r[s];
+        }
+    }
+    for (int s = k - 1; s >= 0; --s) {
+        double t = r[s];
+        for (int j = s + 1; j < k; ++j) t -= M[s][j] * r[j];
+        r[s] = t / M[s][s];
+    }
+    return 0;
+}
+
+/* Swap the adjacent blocks at st (sizes p then q) of the n x n quasi-triangular
+ * S, applying the transformation to all of S and to the columns of Z.  Returns
+ * 0, or 1 if the swap is rejected (S and Z unchanged). */
+int neig_oracle_swap(int n, double *S, int lds, double *Z, int ldz, int st, int p, int q) {
+    const int N = p + q;
+    if (p < 1 || p > 2 || q < 1 || q > 2 || st < 0 || st + N > n) return 2;
+    double B[4][4];
+    double bnorm = 0.0;
+    for (int i = 0; i < N; ++i)
+        for (int j = 0; j < N; ++j) {
+            B[i][j] = S[(st + i) + (size_t)(st + j) * lds];
+            bnorm += B[i][j] * B[i][j];
+        }
+    bnorm = sqrt(bnorm);
+    /* Sylvester A X - X C = B12 with X p x q: unknown X(i,j) at index i + p j */
+    double M[4][4] = {{0}}, r[4] = {0};
+    const int K = p * q;
+    for (int j = 0; j < q; ++j)
+        for (int i = 0; i < p; ++i) {
+            const int row = i + p * j;
+            r[row] = B[i][p + j];
+            for (int k = 0; k < p; ++k) M[row][k + p * j] += B[i][k];
+            for (int k = 0; k < q; ++k) M[row][i + p * k] -= B[p + k][p + j];
+        }
+    if (solve_small(K, M, r)) return 1;
+    /* Y = [-X; I] (N x q), Householder QR, Q accumulated (N x N) */
+    double Y[4][2], Q[4][4];
+    for (int i = 0; i < N; ++i)
+        for (int j = 0; j < q; ++j) Y[i][j] = (i < p) ? -r[i + p * j] : ((i - p == j) ? 1.0 : 0.0);
+    for (int i = 0; i < N; ++i)
+        for (int j = 0; j < N; ++j) Q[i][j] = (i == j) ? 1.0 : 0.0;
+    for (int c = 0; c < q; ++c) {
+        double v[4];
+        for (int t = 0; t < N - c; ++t) v[t] = Y[c + t][c];
+        const double tau = house(N - c, v);
+        if (tau == 0.0) continue;
+        v[0] = 1.0;
+        /* Y <- (I - tau v v^T) Y on rows c.., Q <- Q (I - tau v v^T) on columns c.. */
+        for (int j = c; j < q; ++j) {
+            double d = 0.0;
+            for (int t = 0; t < N - c; ++t) d += v[t] * Y[c + t][j];
+            for (int t = 0; t < N - c; ++t) Y[c + t][j] -= tau * d * v[t];
+        }
+        for (int i = 0; i < N; ++i) {
+            double d = 0.0;
+            for (int t = 0; t < N - c; ++t) d += Q[i][c + t] * v[t];
+            for (int t = 0; t < N - c; ++t) Q[i][c + t] -= tau * d * v[t];
+        }
+    }
+    /* Bn = Q^T B Q; tests on the lower-left q... block */
+    double W[4][4], Bn[4][4];
+    for (int i = 0; i < N; ++i)
+        for (int j = 0; j < N; ++j) {
+            double d = 0.0;
+            for (int k = 0; k < N; ++k) d += B[i][k] * Q[k][j];
+            W[i][j] = d;
+        }
+    for (int i = 0; i < N; ++i)
+        for (int j = 0; j < N; ++j) {
+            double d = 0.0;
+            for (int k = 0; k < N; ++k) d += Q[k][i] * W[k][j];
+            Bn[i][j] = d;
+        }
+    const double thresh = fmax(20.0 * DBL_EPSILON * bnorm, DBL_MIN);
+    double low = 0.0;
+    for (int i = q; i < N; ++i)
+        for (int j = 0; j < q; ++j) {
+            low = fmax(low, fabs(Bn[i][j]));
+            Bn[i][j] = 0.0;
+        }
+    if (low > thresh) return 1;
+    double err = 0.0;
+    for (int i = 0; i < N; ++i)
+        for (int j = 0; j < N; ++j) {
+            double d = 0.0;
+            for (int k = 0; k < N; ++k)
+                for (int l = 0; l < N; ++l) d += Q[i][k] * Bn[k][l] * Q[j][l];
+            err = fmax(err, fabs(d - B[i][j]));
+        }
+    if (err > thresh) return 1;
+    /* apply: rows st..st+N-1 right of the pair, columns above it, Z, the block */
+    for (int j = st + N; j < n; ++j) {
+        double o[4];
+        for (int i = 0; i < N; ++i) o[i] = S[(st + i) + (size_t)j * lds];
+        for (int i = 0; i < N; ++i) {
+            double d = 0.0;
+            for (int k = 0; k < N; ++k) d += Q[k][i] * o[k];
+            S[(st + i) + (size_t)j * lds] = d;
+        }
+    }
+    for (int i = 0; i < st; ++i) {
+        double o[4];
+        for (int k = 0; k < N; ++k) o[k] = S[i + (size_t)(st + k) * lds];
+        for (int j = 0; j < N; ++j) {
+            double d = 0.0;
+            for (int k = 0; k < N; ++k) d += o[k] * Q[k][j];
+            S[i + (size_t)(st + j) * lds] = d;
+        }
+    }
+    for (int i = 0; i < n; ++i) {
+        double o[4];
+        for (int k = 0; k < N; ++k) o[k] = Z[i + (size_t)(st + k) * ldz];
+        for (int j = 0; j < N; ++j) {
+            double d = 0.0;
+            for (int k = 0; k < N; ++k) d += o[k] * Q[k][j];
+            Z[i + (size_t)(st + j) * ldz] = d;
+        }
+    }
+    for (int i = 0; i < N; ++i)
+        for (int j = 0; j < N; ++j) S[(st + i) + (size_t)(st + j) * lds] = Bn[i][j];
+    /* the new 2x2 blocks in standard form */
+    if (q == 2) {
+        double cs, sn, r1, i1, r2, i2;
+        double *a = &S[st + (size_t)st * lds], *b = &S[st + (size_t)(st + 1) * lds];
+        double *c = &S[(st + 1) + (size_t)st * lds], *d = &S[(st + 1) + (size_t)(st + 1) * lds];
+        neig_oracle_std2x2(a, b, c, d, &cs, &sn, &r1, &i1, &r2, &i2);
+        /* rows st, st+1 right of the block and columns above it, Z */
+        for (int j = st + 2; j < n; ++j) {
+            const double x = S[st + (size_t)j * lds], y = S[st + 1 + (size_t)j * lds];
+            S[st + (size_t)j * lds] = cs * x + sn * y;
+            S[st + 1 + (size_t)j * lds] = -sn * x + cs * y;
+        }
+        for (int i = 0; i < st; ++i) {
+            const double x = S[i + (size_t)st * lds], y = S[i + (size_t)(st + 1) * lds];
+            S[i + (size_t)st * lds] = cs * x + sn * y;
+            S[i + (size_t)(st + 1) * lds] = -sn * x + cs * y;
+        }
+        for (int i = 0; i < n; ++i) {
+            const double x = Z[i + (size_t)st * ldz], y = Z[i + (size_t)(st + 1) * ldz];
+            Z[i + (size_t)st * ldz] = cs * x + sn * y;
+            Z[i + (size_t)(st + 1) * ldz] = -sn * x + cs * y;
+        }
+    }
+    if (p == 2) {
+        const int s2 = st + q;
+        double cs, sn, r1, i1, r2, i2;
+        double *a = &S[s2 + (size_t)s2 * lds], *b = &S[s2 + (size_t)(s2 + 1) * lds];
+        double *c = &S[(s2 + 1) + (size_t)s2 * lds], *d = &S[(s2 + 1) + (size_t)(s2 + 1) * lds];
+        neig_oracle_std2x2(a, b, c, d, &cs, &sn, &r1, &i1, &r2, &i2);
+        for (int j = s2 + 2; j < n; ++j) {
+            const double x = S[s2 + (size_t)j * lds], y = S[s2 + 1 + (size_t)j * lds];
+            S[s2 + (size_t)j * lds] = cs * x + sn * y;
+            S[s2 + 1 + (size_t)j * lds] = -sn * x + cs * y;
+        }
+        for (int i = 0; i < s2; ++i) {
+            const double x = S[i + (size_t)s2 * lds], y = S[i + (size_t)(s2 + 1) * lds];
+            S[i + (size_t)s2 * lds] = cs * x + sn * y;
+            S[i + (size_t)(s2 + 1) * lds] = -sn * x + cs * y;
+        }
+        for (int i = 0; i < n; ++i) {
+            const double x = Z[i + (size_t)s2 * ldz], y = Z[i + (size_t)(s2 + 1) * ldz];
+            Z[i + (size_t)s2 * ldz] = cs * x + sn * y;
+            Z[i + (size_t)(s2 + 1) * ldz] = -sn * x + cs * y;
+        }
+    }
+    return 0;
+}
+
+/* Reorder the standardised real Schur form S (n x n) so that the eigenvalues
+ * with select[j] != 0 (either entry of a 2x2 block selects the pair) occupy the
+ * leading diagonal block, keeping their relative order: each selected block,
+ * top to bottom, is moved up by adjacent swaps to just below the ones already
+ * placed.  Z_out = Z_in Q.  *m receives the number of selected eigenvalues;
+ * (wr, wi) are read off the reordered S.  Returns 0, or 1 if a swap was
+ * rejected (S, Z then hold the partly reordered, still valid Schur form). */
+int neig_oracle_reorder(int n, double *S, int lds, double *Z, int ldz, const int *select, double *wr, double *wi,
+                        int *m) {
+    /* block starts and sizes, with their selection */
+    int *bsel = (int *)malloc(sizeof(int) * (size_t)(n + 1));
+    int info = 0, placed = 0;
+    for (int j = 0; j < n; ++j) bsel[j] = select[j] != 0;
+    for (int j = 0; j + 1 < n; ++j)
+        if (S[(j + 1) + (size_t)j * lds] != 0.0) {
+            const int s2 = bsel[j] || bsel[j + 1];
+            bsel[j] = bsel[j + 1] = s2;
+            ++j;
+        }
+    int j = 0;
+    while (j < n) {
+        const int bs = (j + 1 < n && S[(j + 1) + (size_t)j * lds] != 0.0) ? 2 : 1;
+        if (!bsel[j]) {
+            j += bs;
+            continue;
+        }
+        /* move the block at j up to position placed */
+        int pos = j;
+        while (pos > placed) {
+            const int ba = (pos - 2 >= placed && S[(pos - 1) + (size_t)(pos - 2) * lds] != 0.0) ? 2 : 1;
+            const int st = pos - ba;
+            if (neig_oracle_swap(n, S, lds, Z, ldz, st, ba, bs)) {
+                info = 1;
+                break;
+            }
+            /* the selection flags travel with the blocks */
+            for (int t = 0; t < bs; ++t) bsel[st + t] = 1;
+            for (int t = 0; t < ba; ++t) bsel[st + bs + t] = 0;
+            pos = st;
+        }
+        if (info) break;
+        placed += bs;
+        j += bs;
+    }
+    *m = placed;
+    free(bsel);
+    /* eigenvalues in diagonal order */
+    for (int k = 0; k < n;) {
+        if (k + 1 < n && S[(k + 1) + (size_t)k * lds] != 0.0) {
+            const double a = S[k + (size_t)k * lds], b = S[k + (size_t)(k + 1) * lds];
+            const double c = S[(k + 1) + (size_t)k * lds];
+            const double im = sqrt(fabs(b)) * sqrt(fabs(c));
+            wr[k] = wr[k + 1] = a;
+            wi[k] = im;
+            wi[k + 1] = -im;
+            k += 2;
+        } else {
+            wr[k] = S[k + (size_t)k * lds];
+            wi[k] = 0.0;
+            ++k;
+        }
+    }
+    return info;
+}
