@@ -193,6 +193,28 @@ int neig_aed(int n, double *H, int ldh, double *Z, int ldz, int ktop, int kbot, 
  */
 int neig_small_schur(int n, double *H, int ldh, double *Z, int ldz, double *wr, double *wi, hipStream_t stream);
 
+/*
+ * neig_reorder -- eigenvalue reordering of a real Schur decomposition (the
+ * phase the paper runs after the Schur reduction): an orthogonal Q such that
+ * the selected eigenvalues occupy the leading diagonal block of Q^T S Q, in
+ * their original order, by exchanges of adjacent diagonal blocks (the
+ * Sylvester-equation construction of Bai and Demmel), organised in windows of
+ * at most 96 rows whose factors are applied to the rest of S and to Z with
+ * FP64 matrix-core products.
+ *   S, lds   device; on entry a standardised real Schur form (as neig_schur
+ *            returns it); on exit the reordered one.
+ *   Z, ldz   device; on exit Z_in * Q.
+ *   select   host int[n]; nonzero selects the eigenvalue at that diagonal
+ *            position (either position of a 2x2 block selects the pair).
+ *   wr, wi   device, n doubles each: eigenvalues of the reordered S.
+ *   m        host out: number of selected eigenvalues now leading.
+ * Synchronous.  Returns 0; 1 if an exchange was rejected by its stability test
+ * (S, Z then hold a valid, partly reordered Schur decomposition and *m counts
+ * the eigenvalues in place); -k for invalid argument k; <= -100 HIP error.
+ */
+int neig_reorder(int n, double *S, int lds, double *Z, int ldz, const int *select, double *wr, double *wi, int *m,
+                 hipStream_t stream);
+
 /* Set / read the tunables (process-wide).  neig_set_params returns -k when field k
  * is out of range. */
 int neig_set_params(const neig_params *p);

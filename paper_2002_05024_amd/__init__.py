@@ -23,6 +23,7 @@ from .binding import (  # noqa: F401
     sweep,
     aed,
     small_schur,
+    reorder,
     finalize,
     policy_bins,
     policy_set,

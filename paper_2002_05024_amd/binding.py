@@ -112,6 +112,7 @@ def load_library():
         "neig_mlp_grad": [_i, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp],
         "neig_mlp_adam": [_vp, _vp, _vp, _vp, _i, ctypes.c_float, _vp],
         "neig_mlp_infer": [_i, _vp, _vp, _vp, _vp, _vp, _vp],
+        "neig_reorder": [_i, _vp, _i, _vp, _i, _ip, _vp, _vp, _ip, _vp],
     }
     for name, args in sigs.items():
         fn = getattr(lib, name)
@@ -442,6 +443,30 @@ def mlp_infer(X, theta, stream=None):
                             ctypes.c_void_p(conf.data_ptr()), _stream_ptr(stream))
     _raise("neig_mlp_infer", rc)
     return logits, bins, conf
+
+
+def reorder(S, Z, select, stream=None):
+    """Move the selected eigenvalues (host sequence of 0/1 per diagonal position)
+    of the Schur form S (device, in place) to the leading block; Z updated in
+    place.  Returns (wr, wi, m, info)."""
+    import numpy as np
+
+    torch = _torch()
+    lib = load_library()
+    n = int(S.shape[0])
+    lds = _check_matrix("S", S, n)
+    ldz = _check_matrix("Z", Z, n)
+    sel = np.ascontiguousarray(select, dtype=np.int32)
+    if sel.size != n:
+        raise NeigError("reorder: select needs one entry per diagonal position")
+    wr = torch.empty(n, dtype=torch.float64, device=S.device)
+    wi = torch.empty(n, dtype=torch.float64, device=S.device)
+    m = ctypes.c_int()
+    info = lib.neig_reorder(n, ctypes.c_void_p(S.data_ptr()), lds, ctypes.c_void_p(Z.data_ptr()), ldz,
+                            sel.ctypes.data_as(_ip), ctypes.c_void_p(wr.data_ptr()), ctypes.c_void_p(wi.data_ptr()),
+                            ctypes.byref(m), _stream_ptr(stream))
+    _raise("neig_reorder", info)
+    return wr, wi, m.value, info
 
 
 def set_params(**kw) -> None:

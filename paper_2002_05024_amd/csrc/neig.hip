@@ -148,7 +148,7 @@ DeviceWs &workspace() {
     while (c > 8 && (size_t)(2 * (c + 1) * (c + 2)) * 8 + 2048 > w.lds_max) --c;
     w.chase_max = c;
     for (const void *fn : {(const void *)k_small_qr, (const void *)k_aed, (const void *)k_chase,
-                           (const void *)k_update, (const void *)k_batched})
+                           (const void *)k_update, (const void *)k_batched, (const void *)k_reorder_window})
         allow_dynamic_lds(fn, w.lds_max);
     ck(hipDeviceGetAttribute(&w.cus, hipDeviceAttributeMultiprocessorCount, dev));
     ck(hipMalloc((void **)&w.ist, kStatusInts * sizeof(int)));
@@ -769,7 +769,80 @@ class Solver {
 
     std::vector<PolicySample> policy_log_;
 
-    // Standardise any 2x2 block not yet in standard form, then read off (wr, wi).
+    // ---- eigenvalue reordering -----------------------------------------------
+    // Move the eigenvalues flagged in sel (per diagonal position; a 2x2 block is
+    // selected as a whole) to the leading diagonal block, keeping their order.
+    // Windows of at most REORDER_WMAX rows: in each, the selected blocks go to
+    // the window's top (k_reorder_window) and the window's factor is applied to
+    // the rest of S and to Z by the update kernel.  The next window starts at
+    // the first selected block not yet in place, reaching at most REORDER_WMAX
+    // rows up, so each window moves that block up by most of a window.
+    // Returns 0, or 1 when a swap was rejected (S, Z remain a valid Schur
+    // decomposition, partly reordered).  *m = selected eigenvalues in place.
+    int reorder(std::vector<int> sel, int *m_out) {
+        const int n = n_;
+        const int W = std::min(REORDER_WMAX, nsmall_);
+        std::vector<char> nz(n + 1, 0);  // nz[i]: rows i-1, i form a 2x2 block
+        {
+            std::vector<double> g = gather(0, n - 1);
+            for (int i = 1; i < n; ++i) nz[i] = g[n + i] != 0.0;
+        }
+        auto bsize = [&](int j) { return (j + 1 < n && nz[j + 1]) ? 2 : 1; };
+        for (int j = 0; j < n;) {  // a pair is selected as a whole
+            const int bs = bsize(j);
+            const int v = (sel[j] || (bs == 2 && sel[j + 1])) ? 1 : 0;
+            for (int t = 0; t < bs; ++t) sel[j + t] = v;
+            j += bs;
+        }
+        int total = 0;
+        for (int j = 0; j < n; ++j) total += sel[j];
+        grow(&ws_.vt, &ws_.vt_cap, (size_t)W * W);
+        int placed = 0, info = 0;
+        while (placed < total) {
+            int p = placed;
+            while (p < n && !sel[p]) p += bsize(p);
+            if (p >= n) break;
+            const int bs = bsize(p);
+            if (p == placed) {
+                placed += bs;
+                continue;
+            }
+            int lo = std::max(placed, p + bs - W);
+            if (lo > placed && nz[lo]) ++lo;      // do not split the 2x2 block at lo-1, lo
+            int hi = std::min(n, lo + W);
+            if (hi < n && nz[hi]) --hi;           // nor the one at hi-1, hi
+            const int w = hi - lo;
+            ReorderFlags f;
+            std::memset(&f, 0, sizeof(f));
+            for (int t = 0; t < w; ++t) f.sel[t] = sel[lo + t];
+            const size_t lds = (size_t)(2 * w * (w + 1)) * sizeof(double);
+            timed(kSmall, [&] {
+                hipLaunchKernelGGL(k_reorder_window, dim3(1), dim3(NT), lds, st_, H_, ldh_, lo, w, f, ws_.vt, w,
+                                   ws_.ist);
+                ck(hipGetLastError());
+            });
+            std::vector<Task> tasks;
+            add_block_updates(tasks, lo, hi - 1, ws_.vt, w);
+            run_updates(tasks);
+            ck(hipMemcpyAsync(ws_.h_ist, ws_.ist, 2 * sizeof(int), hipMemcpyDeviceToHost, st_));
+            std::vector<double> g = gather(lo, hi - 1);  // also waits for the status copy
+            const int k = ws_.h_ist[0];
+            for (int t = 0; t < w; ++t) {
+                sel[lo + t] = t < k ? 1 : 0;
+                if (t > 0) nz[lo + t] = g[w + t] != 0.0;
+            }
+            stats_.small_solves++;
+            if (ws_.h_ist[1]) {
+                info = 1;
+                break;
+            }
+            if (lo == placed) placed += k;
+        }
+        *m_out = placed;
+        return info;
+    }
+
+    // Standardise any 2x2 block not yet in standard form, then (wr, wi).
     void finish_std() {
         if (n_ < 2) return;
         grow(&ws_.flag, &ws_.flag_cap, (size_t)n_);
@@ -841,6 +914,30 @@ extern "C" int neig_schur(int n, double *H, int ldh, double *Z, int ldz, double 
         int info = s.run();
         g_policy_log.swap(s.policy_log_);
         if (info == -2) return -2;
+        s.eigenvalues(wr, wi);
+        s.sync();
+        g_stats = s.stats_;
+        return info;
+    } catch (const HipFail &f) {
+        return -100 - (int)f.e;
+    }
+}
+
+extern "C" int neig_reorder(int n, double *S, int lds, double *Z, int ldz, const int *select, double *wr, double *wi,
+                            int *m, hipStream_t stream) {
+    int a = check_args(n, S, lds, Z, ldz);
+    if (a) return a;
+    if (n > 0 && !select) return -6;
+    if (n > 0 && !wr) return -7;
+    if (n > 0 && !wi) return -8;
+    if (!m) return -9;
+    *m = 0;
+    if (n == 0) return 0;
+    std::lock_guard<std::mutex> lock(g_mutex);
+    try {
+        Solver s(n, S, lds, Z, ldz, stream);
+        std::vector<int> sel(select, select + n);
+        const int info = s.reorder(sel, m);
         s.eigenvalues(wr, wi);
         s.sync();
         g_stats = s.stats_;

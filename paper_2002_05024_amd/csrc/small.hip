@@ -982,3 +982,64 @@ k_aed(double *H, int ldh, int ktop, int kbot, int nw, double hnorm, double smlnu
     lds_store(H, ldh, kwtop, nw, T, ld, V, ld, Vt, ldvt);
     if (kwtop > ktop && threadIdx.x == 0) AT(H, ldh, kwtop, kwtop - 1) = o.spike0;
 }
+
+// ---------------------------------------------------------------- reordering window
+
+#define REORDER_WMAX 96
+
+struct ReorderFlags {
+    int sel[REORDER_WMAX];  // 1 at the positions of selected eigenvalues of the window
+};
+
+// Reorder a w x w diagonal window of the quasi-triangular S at (off, off): the
+// selected blocks move to the top of the window in their order, by swaps of
+// adjacent diagonal blocks (the block exchange the paper's reordering phase
+// uses), with the window's orthogonal factor accumulated in LDS.  The window
+// must not split a 2x2 block.  Afterwards every 2x2 block of the window is put
+// in standard form.  Outputs: the window back in S, its factor transposed in
+// Vt, status[0] = selected eigenvalues now at the top, status[1] = 1 if a swap
+// was rejected (the window is then partly reordered, still a valid Schur form).
+// The caller applies Vt to the rest of S and to Z.
+extern "C" __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(1, 1)))
+k_reorder_window(double *S, int lds_, int off, int w, ReorderFlags f, double *Vt, int ldvt, int *status) {
+    extern __shared__ double lds[];
+    const int ld = w + 1;
+    double *T = lds, *V = lds + (size_t)w * ld;
+    lds_load_block(S, lds_, off, w, T, ld, V, ld);
+    int placed = 0, fail = 0, j = 0;
+    while (j < w) {
+        const int bs = (j + 1 < w && AT(T, ld, j + 1, j) != 0.0) ? 2 : 1;
+        if (!f.sel[j]) {
+            j += bs;
+            continue;
+        }
+        int pos = j;
+        while (pos > placed) {
+            const int ba = (pos - 2 >= placed && AT(T, ld, pos - 1, pos - 2) != 0.0) ? 2 : 1;
+            const int st = pos - ba;
+            if (!lds_swap(T, ld, V, ld, w, st, ba, bs)) {
+                fail = 1;
+                break;
+            }
+            pos = st;
+        }
+        if (fail) break;
+        placed += bs;
+        j += bs;
+    }
+    // standard form for every 2x2 block of the window (swaps leave them in any form)
+    for (int k = 0; k + 1 < w;) {
+        if (AT(T, ld, k + 1, k) != 0.0) {
+            const double a = AT(T, ld, k, k), b = AT(T, ld, k, k + 1), c = AT(T, ld, k + 1, k), d = AT(T, ld, k + 1, k + 1);
+            if (!(a == d && b * c < 0.0)) lds_standardise(T, ld, V, ld, w, k);
+            k += 2;
+        } else {
+            ++k;
+        }
+    }
+    lds_store(S, lds_, off, w, T, ld, V, ld, Vt, ldvt);
+    if (threadIdx.x == 0) {
+        status[0] = placed;
+        status[1] = fail;
+    }
+}

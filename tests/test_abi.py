@@ -21,7 +21,8 @@ def test_header_declares_the_boundary():
     names = declared_functions()
     for required in ["neig_schur", "neig_schur_batched", "neig_sweep", "neig_aed", "neig_small_schur",
                      "neig_set_params", "neig_get_params", "neig_get_stats", "neig_finalize", "neig_version",
-                     "neig_set_batched_tune", "neig_get_batched_tune"]:
+                     "neig_set_batched_tune", "neig_get_batched_tune", "neig_reorder", "neig_policy_set",
+                     "neig_mlp_grad", "neig_mlp_infer"]:
         assert required in names
 
 
