@@ -52,6 +52,8 @@ def parse():
                     help="time this many of the batch's problems solved one neig_schur call at a time")
     ap.add_argument("--single", type=int, default=1, help="run the n=20000 single-matrix workload")
     ap.add_argument("--reorder", type=int, default=1, help="also time the eigenvalue reordering at n=4000")
+    ap.add_argument("--hessenberg", type=int, default=20000,
+                    help="order of the dense matrix for the Hessenberg-reduction leg (0 skips it)")
     return ap.parse_args()
 
 
@@ -217,6 +219,54 @@ def reorder_leg(args, dev):
             "gflops_update_executed": round(st["gemm_flops"] / min(times) / 1e9, 2)}
 
 
+def hessenberg_leg(args, dev):
+    """Hessenberg reduction of a dense N(0,1) matrix (the step before the Schur
+    reduction), Q1 accumulated from the identity; one warm-up at a small order,
+    then one timed reduction (events around neig_hessenberg) and the
+    backward-error / orthogonality check with GPU products."""
+    import numpy as np
+    import torch
+
+    from paper_2002_05024_amd import binding, inputs
+
+    n = args.hessenberg
+    w = torch.from_numpy(np.ascontiguousarray(inputs.rng(inputs.FULL, 77).standard_normal((256, 256)))).to(dev)
+    binding.hessenberg(w.t().contiguous().t())
+    g = inputs.rng(inputs.FULL, 78)
+    A0 = torch.from_numpy(g.standard_normal((n, n))).to(dev).t()  # column-major view of the row-major fill
+    A = A0.clone(memory_format=torch.preserve_format)
+    Q = torch.eye(n, dtype=torch.float64, device=dev).t()  # column-major view
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    binding.hessenberg(A, Q)
+    e1.record()
+    torch.cuda.synchronize()
+    sec = e0.elapsed_time(e1) / 1000.0
+    flops = 10.0 / 3.0 * n ** 3
+    gemv_bytes = 8.0 * n ** 3 / 3.0  # each column's product reads the trailing block once
+    out = {"workload": f"Hessenberg reduction of a dense N(0,1) matrix, n={n}, Q1 accumulated",
+           "seconds": round(sec, 3), "gflops_reduction": round(flops / sec / 1e9, 1),
+           "gemv_bytes_algorithmic": gemv_bytes, "gemv_hbm_floor_s": round(gemv_bytes / 8e12, 3),
+           "paper_context": "Table 2, n=20000: 53 s (14 Xeon Gold 6132 cores + Tesla V100), 49 s MAGMA"}
+    if args.check:
+        nrm = torch.linalg.norm(A0)
+        R = Q @ A
+        R = R @ Q.t()
+        R -= A0
+        be = float(torch.linalg.norm(R) / nrm)
+        del R
+        E = Q.t() @ Q
+        E.diagonal().sub_(1.0)
+        oe = float(torch.linalg.norm(E))
+        del E
+        out["check"] = {"backward_error": be, "orthogonality": oe, "bound_50n_eps": 50 * n * 2.0 ** -52,
+                        "below_subdiagonal_zero": bool(float(torch.tril(A, -2).abs().max()) == 0.0)}
+    del A, A0, Q
+    torch.cuda.empty_cache()
+    return out
+
+
 def batched_leg(args, dev):
     """The batched workload: ``batch_count`` problems with n uniform in [32, 1024],
     half random N(0,1) Hessenberg and half prescribed-spectrum Hessenberg, Z from
@@ -322,7 +372,13 @@ def main():
     binding.load_library()
     if not args.single:
         line = {"metric": "Schur reduction seconds + FP64 GFLOP/s at n=20000; batched solves/sec",
-                "n_gpus": 1, "dtype": "f64", "data": "synthetic", "batched": batched_leg(args, dev)}
+                "n_gpus": 1, "dtype": "f64", "data": "synthetic"}
+        if args.batched:
+            line["batched"] = batched_leg(args, dev)
+        if args.reorder:
+            line["reorder"] = reorder_leg(args, dev)
+        if args.hessenberg:
+            line["hessenberg"] = hessenberg_leg(args, dev)
         print(json.dumps(line), flush=True)
         return
     n = args.n
@@ -401,13 +457,15 @@ def main():
     if args.check:
         be, oe = backward_and_orth(H0, H, Z)
         line["check"] = {"backward_error": be, "orthogonality": oe, "bound_50n_eps": 50 * n * 2.0 ** -52}
-    if args.batched or args.reorder:
+    if args.batched or args.reorder or args.hessenberg:
         del H, Z, H0
         torch.cuda.empty_cache()
     if args.batched:
         line["batched"] = batched_leg(args, dev)
     if args.reorder:
         line["reorder"] = reorder_leg(args, dev)
+    if args.hessenberg:
+        line["hessenberg"] = hessenberg_leg(args, dev)
     if args.cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(args.cpu_n, n)
     print(json.dumps(line), flush=True)

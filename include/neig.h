@@ -55,7 +55,10 @@ typedef struct neig_params {
                       1: the proposal network installed by neig_policy_set, falling back to
                          the default rules when it is not confident;
                       2: exploration: uniformly random bins (seeded by `seed`), every
-                         decision logged for neig_policy_log                              */
+                         decision logged for neig_policy_log;
+                      3: fixed bins for the whole call, shift bin seed mod 8 and window
+                         bin (seed / 8) mod 8, every decision logged (per-run
+                         exploration)                                                     */
     int seed;      /* seed of the exploration generator                                  */
     int reserved[4];
 } neig_params;
@@ -194,6 +197,27 @@ int neig_aed(int n, double *H, int ldh, double *Z, int ldz, int ktop, int kbot, 
 int neig_small_schur(int n, double *H, int ldh, double *Z, int ldz, double *wr, double *wi, hipStream_t stream);
 
 /*
+ * neig_hessenberg -- reduction of a general matrix to upper Hessenberg form,
+ * A = Q1 H Q1^T (Section 2, eq. 3; the step before the Schur reduction), by
+ * the standard blocked Householder algorithm of Section 3.1: panels of 64
+ * reflectors reduced with the trailing matrix-vector products on the GPU,
+ * accumulated as I - V T V^T with Y = A V T, then the trailing-matrix and
+ * top-part updates as FP64 matrix-core products.  Reflector convention:
+ * P = I - tau v v^T, v(0) = 1, beta = -sign(alpha) ||x|| (sign(0) = +1),
+ * tau = 0 when the tail below the subdiagonal is already zero.
+ *   n            order (>= 0).
+ *   A, lda       device, column-major; on entry the general matrix, on exit H
+ *                with exact zeros below the first subdiagonal.
+ *   Q, ldq       device, column-major, or NULL; on exit Q_in * Q1 (pass the
+ *                identity for Q1 itself).  NULL skips the accumulation.
+ * Workspace (about 4 * 64 * n doubles plus partials) is cached per device.
+ * Synchronous.  Returns 0; -1 n < 0; -2 A null; -3 lda < max(1, n);
+ * -5 ldq < max(1, n) with Q given; <= -100 HIP error.  Non-finite entries
+ * propagate.
+ */
+int neig_hessenberg(int n, double *A, int lda, double *Q, int ldq, hipStream_t stream);
+
+/*
  * neig_reorder -- eigenvalue reordering of a real Schur decomposition (the
  * phase the paper runs after the Schur reduction): an orthogonal Q such that
  * the selected eigenvalues occupy the leading diagonal block of Q^T S Q, in
@@ -264,7 +288,7 @@ int neig_policy_set(const float *theta, int nparam, float min_conf);
 
 /*
  * neig_policy_log -- the decisions of the most recent neig_schur call with
- * policy 1 or 2.  For decision i < min(count, cap): feat[24 i ..] its features,
+ * policy 1, 2 or 3.  For decision i < min(count, cap): feat[24 i ..] its features,
  * bins[2 i ..] the (shift, window) bins applied (or proposed, when the default
  * rules decided), stats[4 i ..] = deflations of the next window, milliseconds
  * from the decision to the end of that window, the order m of the active

@@ -24,6 +24,7 @@ from .binding import (  # noqa: F401
     aed,
     small_schur,
     reorder,
+    hessenberg,
     finalize,
     policy_bins,
     policy_set,

@@ -113,6 +113,7 @@ def load_library():
         "neig_mlp_adam": [_vp, _vp, _vp, _vp, _i, ctypes.c_float, _vp],
         "neig_mlp_infer": [_i, _vp, _vp, _vp, _vp, _vp, _vp],
         "neig_reorder": [_i, _vp, _i, _vp, _i, _ip, _vp, _vp, _ip, _vp],
+        "neig_hessenberg": [_i, _vp, _i, _vp, _i, _vp],
     }
     for name, args in sigs.items():
         fn = getattr(lib, name)
@@ -443,6 +444,25 @@ def mlp_infer(X, theta, stream=None):
                             ctypes.c_void_p(conf.data_ptr()), _stream_ptr(stream))
     _raise("neig_mlp_infer", rc)
     return logits, bins, conf
+
+
+def hessenberg(A, Q=None, accumulate=True, stream=None):
+    """Reduce A (device FP64, column-major, in place) to upper Hessenberg form.
+    With ``accumulate`` the orthogonal factor is applied to Q (identity when Q
+    is None) and returned: A_in = Q H Q^T for Q_in = I.  Returns Q or None."""
+    torch = _torch()
+    lib = load_library()
+    n = int(A.shape[0])
+    lda = _check_matrix("A", A, n)
+    qp, ldq = None, 1
+    if accumulate:
+        if Q is None:
+            Q = torch.eye(n, dtype=torch.float64, device=A.device).t().contiguous().t()
+        ldq = _check_matrix("Q", Q, n)
+        qp = ctypes.c_void_p(Q.data_ptr())
+    info = lib.neig_hessenberg(n, ctypes.c_void_p(A.data_ptr()), lda, qp, ldq, _stream_ptr(stream))
+    _raise("neig_hessenberg", info)
+    return Q if accumulate else None
 
 
 def reorder(S, Z, select, stream=None):

@@ -16,6 +16,7 @@
 #include "util.hip"
 #include "batched.hip"
 #include "mlp.hip"
+#include "hessenberg.hip"
 
 #include <algorithm>
 #include <chrono>
@@ -121,6 +122,10 @@ struct DeviceWs {
     float *pol_out = nullptr;
     float *h_pol_out = nullptr;
     float *mlp_part = nullptr; size_t mlp_part_cap = 0;
+    // Hessenberg reduction: V, Y, T, partials (one block, carved per call) and
+    // the column state with its two workgroup counters (zero between launches)
+    double *hrd = nullptr; size_t hrd_cap = 0;
+    HrdState *hrd_st = nullptr;
 };
 
 DeviceWs g_ws[kMaxDevices];
@@ -167,7 +172,7 @@ void free_workspace(DeviceWs &w) {
     if (!w.ready) return;
     for (void *p : {(void *)w.ut, (void *)w.vt, (void *)w.poly, (void *)w.dbuf, (void *)w.rot, (void *)w.ist,
                     (void *)w.flag, (void *)w.bprob, (void *)w.border, (void *)w.bnext,
-                    (void *)w.theta, (void *)w.pol_out, (void *)w.mlp_part})
+                    (void *)w.theta, (void *)w.pol_out, (void *)w.mlp_part, (void *)w.hrd, (void *)w.hrd_st})
         if (p) (void)hipFree(p);
     for (void *p : {(void *)w.h_ist, (void *)w.h_dbuf, (void *)w.h_poly, (void *)w.h_flag, (void *)w.h_pol_out})
         if (p) (void)hipHostFree(p);
@@ -709,6 +714,11 @@ class Solver {
                     bns = explore_bin();
                     bnw = explore_bin();
                     used = 1;
+                } else if (mode == 3) {
+                    const unsigned sd = (unsigned)p_.seed;
+                    bns = (int)(sd % MLP_NBIN);
+                    bnw = (int)((sd / MLP_NBIN) % MLP_NBIN);
+                    used = 1;
                 } else if (!g_policy.theta.empty() && d.conf[0] >= g_policy.min_conf &&
                            d.conf[1] >= g_policy.min_conf) {
                     used = 1;
@@ -889,6 +899,92 @@ class Solver {
     double hnorm_ = 0.0, smlnum_ = 0.0;
 };
 
+// ---------------------------------------------------------------- Hessenberg reduction
+
+// Thin product out = (sum over splits of op(C) V - X B) T (X, T optional) with
+// op(C) M x K, V K x nbc; the long dimension K is split so that the launch has
+// about two workgroups per compute unit.
+void hrd_thin(DeviceWs &ws, double *sk, const double *C, int ldc, int trans, int M, int K, const double *V,
+              int ldv, int nbc, const double *X, int ldx, const double *B, const double *T, double *out, int ldo,
+              hipStream_t s) {
+    if (M <= 0) return;
+    const int rb = (M + 63) / 64;
+    int nsplit = std::max(1, std::min((2 * ws.cus + rb - 1) / rb, (K + 31) / 32));
+    const int kper = ((K + nsplit - 1) / nsplit + 31) / 32 * 32;
+    nsplit = (K + kper - 1) / kper;
+    const size_t sp = (size_t)M * nbc;
+    SkArgs a{C, V, sk, sp, ldc, ldv, M, K, nbc, kper, trans};
+    hipLaunchKernelGGL(k_hrd_skinny, dim3(rb, nsplit), dim3(HRD_THREADS), 0, s, a);
+    RdArgs r{sk, sp, nsplit, X, ldx, B, T, out, ldo, M, nbc};
+    hipLaunchKernelGGL(k_hrd_reduce, dim3(rb), dim3(HRD_THREADS), 0, s, r);
+}
+
+// C (M x N) -= L1 R1^T + L2 R2^T
+void hrd_rank(double *C, int ldc, int M, int N, const double *L1, int ldl1, const double *R1, int ldr1, int r1,
+              const double *L2, int ldl2, const double *R2, int ldr2, int r2, hipStream_t s) {
+    if (M <= 0 || N <= 0) return;
+    RkArgs a{C, L1, R1, L2, R2, ldc, ldl1, ldr1, ldl2, ldr2, M, N, r1, r2};
+    hipLaunchKernelGGL(k_hrd_rank, dim3((M + 63) / 64, (N + 63) / 64), dim3(HRD_THREADS), 0, s, a);
+}
+
+// A (n x n) <- H = Q1^T A Q1 upper Hessenberg; Q <- Q Q1 when Q is given.
+void hessenberg_run(int n, double *A, int lda, double *Q, int ldq, hipStream_t s) {
+    DeviceWs &ws = workspace();
+    if (n <= 2) return;
+    const int NB = HRD_NB;
+    const int ldw = (n + 7) & ~7;
+    const size_t nrb_max = (size_t)(n + HRD_RB - 1) / HRD_RB;
+    const size_t nch_max = (size_t)(n + HRD_GC - 1) / HRD_GC;
+    const size_t sk_cap = ((size_t)128 * ws.cus + (size_t)n + 64) * NB;
+    const size_t need = 4 * (size_t)ldw * NB + 2 * (size_t)NB * NB + nrb_max * (NB + 2) + nch_max * ldw + sk_cap;
+    grow(&ws.hrd, &ws.hrd_cap, need);
+    if (!ws.hrd_st) {
+        ck(hipMalloc((void **)&ws.hrd_st, sizeof(HrdState)));
+        ck(hipMemset(ws.hrd_st, 0, sizeof(HrdState)));
+    }
+    double *V = ws.hrd, *Y = V + (size_t)ldw * NB, *P = Y + (size_t)ldw * NB, *Mt = P + (size_t)ldw * NB;
+    double *T = Mt + (size_t)ldw * NB, *Gt = T + (size_t)NB * NB;
+    double *part = Gt + (size_t)NB * NB, *zpart = part + nrb_max * (NB + 2), *sk = zpart + nch_max * ldw;
+    HrdArgs ha{A, V, Y, T, part, zpart, ws.hrd_st, lda, ldw, n, 0, 0, 0, 0, 0};
+    for (int k0 = 0; k0 < n - 2; k0 += NB) {
+        const int jb = std::min(NB, n - 2 - k0);
+        const int m = n - k0 - 1;
+        const int nrb = (m + HRD_RB - 1) / HRD_RB;
+        ha.k0 = k0;
+        ha.m = m;
+        ha.jb = jb;
+        int nch = 0;
+        for (int i = 0; i <= jb; ++i) {
+            ha.i = i;
+            ha.nch = nch;
+            if (i > 0) hipLaunchKernelGGL(k_hrd_a, dim3(nrb), dim3(HRD_THREADS), 0, s, ha);
+            if (i == jb) break;
+            hipLaunchKernelGGL(k_hrd_b, dim3(nrb), dim3(HRD_THREADS), 0, s, ha);
+            nch = (m - i - 1 + HRD_GC - 1) / HRD_GC;
+            hipLaunchKernelGGL(k_hrd_gemv, dim3((m + HRD_GR - 1) / HRD_GR, nch), dim3(HRD_THREADS), 0, s, ha);
+        }
+        const int nt = n - k0 - jb;  // trailing columns k0 + jb .. n-1
+        double *Atop = A + (size_t)(k0 + 1) * lda;
+        double *At = Atop + (size_t)(jb - 1) * lda + (k0 + 1);
+        // Y(0:k0, :) = A(0:k0, k0+1:n) V T
+        hrd_thin(ws, sk, Atop, lda, 0, k0 + 1, m, V, ldw, jb, nullptr, 0, nullptr, T, Y, ldw, s);
+        // G^T = Y_low^T V;  Mt = (A_t^T V - V_t G^T) T
+        hrd_thin(ws, sk, Y + k0 + 1, ldw, 1, jb, m, V, ldw, jb, nullptr, 0, nullptr, nullptr, Gt, NB, s);
+        hrd_thin(ws, sk, At, lda, 1, nt, m, V, ldw, jb, V + (jb - 1), ldw, Gt, T, Mt, ldw, s);
+        // A_t <- (I - V T V^T)^T (A_t - Y_low V_t^T) = A_t - Y_low V_t^T - V Mt^T
+        hrd_rank(At, lda, m, nt, Y + k0 + 1, ldw, V + (jb - 1), ldw, jb, V, ldw, Mt, ldw, jb, s);
+        // A(0:k0, k0+1:n) -= Y_top V^T
+        hrd_rank(Atop, lda, k0 + 1, m, Y, ldw, V, ldw, jb, nullptr, 0, nullptr, 0, 0, s);
+        if (Q) {
+            // Q(:, k0+1:n) -= (Q(:, k0+1:n) V T) V^T
+            double *Qc = Q + (size_t)(k0 + 1) * ldq;
+            hrd_thin(ws, sk, Qc, ldq, 0, n, m, V, ldw, jb, nullptr, 0, nullptr, T, P, ldw, s);
+            hrd_rank(Qc, ldq, n, m, P, ldw, V, ldw, jb, nullptr, 0, nullptr, 0, 0, s);
+        }
+    }
+    ck(hipGetLastError());
+}
+
 int check_args(int n, const void *H, int ldh, const void *Z, int ldz) {
     if (n < 0) return -1;
     if (n > 0 && !H) return -2;
@@ -942,6 +1038,22 @@ extern "C" int neig_reorder(int n, double *S, int lds, double *Z, int ldz, const
         s.sync();
         g_stats = s.stats_;
         return info;
+    } catch (const HipFail &f) {
+        return -100 - (int)f.e;
+    }
+}
+
+extern "C" int neig_hessenberg(int n, double *A, int lda, double *Q, int ldq, hipStream_t stream) {
+    if (n < 0) return -1;
+    if (n > 0 && !A) return -2;
+    if (lda < std::max(1, n)) return -3;
+    if (Q && ldq < std::max(1, n)) return -5;
+    if (n == 0) return 0;
+    std::lock_guard<std::mutex> lock(g_mutex);
+    try {
+        hessenberg_run(n, A, lda, Q, ldq, stream);
+        ck(hipStreamSynchronize(stream));
+        return 0;
     } catch (const HipFail &f) {
         return -100 - (int)f.e;
     }
@@ -1269,7 +1381,7 @@ extern "C" int neig_set_params(const neig_params *p) {
     if (p->nibble < 0 || p->nibble > 100) return -8;
     if (p->exc < 0) return -9;
     if (p->timing < 0 || p->timing > 1) return -10;
-    if (p->policy < 0 || p->policy > 2) return -11;
+    if (p->policy < 0 || p->policy > 3) return -11;
     std::lock_guard<std::mutex> lock(g_mutex);
     g_params = *p;
     return 0;

@@ -148,6 +148,73 @@ def collect(start: int, count: int, out: str, lo: int, hi: int, seed: int, threa
     _save(out, feats, bins, stats, runs)
 
 
+# Arms of the per-run exploration: (shift bin, window bin) pairs held for a
+# whole solve.  Shift bins 3, 5, 7 = 16, 24, 32 shifts; window bins 3, 5, 6, 7
+# = 48, 64, 80, 96 rows (the default rules use 32 shifts and a 64-row window
+# for active blocks of 300 rows or more).
+ARMS = [(a, b) for a in (3, 5, 7) for b in (3, 5, 6, 7)]
+
+
+def default_bins(m):
+    """The bins of the default rules for an active block of order m."""
+    return (7, 5) if m >= 300 else (3, 3)
+
+
+def collect_runs(start: int, count: int, out: str, lo: int, hi: int, threads: int):
+    """Per-run exploration: every training matrix is solved twice, once with the
+    default rules (``policy = 1`` with no network: the defaults decide and every
+    decision's features are logged) and once with one arm held for the whole
+    solve (``policy = 3``); arms cycle per family.  Stores the decisions of both
+    solves and, per solve, the time of the default solve and its own."""
+    from . import binding
+
+    binding.load_library()
+    binding.policy_set(None)
+    solver = Solver(hi)
+    rec = {"feat": [], "bins": [], "stats": [], "run": [], "t_def": [], "t_run": [], "arm": []}
+    t0 = time.time()
+    for i, fam, H in producer(list(range(start, start + count)), "train", lo, hi, threads):
+        arm = ARMS[(i // 3) % len(ARMS)]
+        binding.set_params(policy=1)
+        t_def, info_d, _, _ = solver.solve(H, check=False)
+        f0, b0, s0 = binding.policy_log()
+        b0 = np.array([default_bins(m) for m in s0[:, 2]], dtype=np.int32).reshape(-1, 2)
+        binding.set_params(policy=3, seed=arm[0] + 8 * arm[1])
+        t_arm, info_a, _, _ = solver.solve(H, check=False)
+        f1, b1, s1 = binding.policy_log()
+        for f, b, st, kind, t in ((f0, b0, s0, -1, t_def), (f1, b1, s1, ARMS.index(arm), t_arm)):
+            rec["feat"].append(f)
+            rec["bins"].append(b)
+            rec["stats"].append(st)
+            rec["run"].append(np.full(len(b), i, dtype=np.int32))
+            rec["t_def"].append(np.full(len(b), t_def, dtype=np.float32))
+            rec["t_run"].append(np.full(len(b), t, dtype=np.float32))
+            rec["arm"].append(np.full(len(b), kind, dtype=np.int32))
+        log(f"[collect-run] {i} {fam} n={H.shape[0]} default {t_def:.2f}s arm {arm} {t_arm:.2f}s "
+            f"info {info_d}/{info_a} elapsed {time.time() - t0:.0f}s")
+        if (i - start + 1) % 10 == 0:
+            _save_runs(out, rec)
+    binding.set_params(policy=0, seed=0)
+    _save_runs(out, rec)
+
+
+def _save_runs(out, rec):
+    tmp = out + ".tmp.npz"
+    np.savez_compressed(tmp, **{k: np.concatenate(v) for k, v in rec.items()})
+    os.replace(tmp, out)
+
+
+def run_weights(t_def, t_run, arm, beta: float = 3.0):
+    """Weights of the per-run data: a decision of an arm's solve counts
+    exp(beta * log(t_default / t_arm)) times the number of arms (each arm is
+    tried on 1/len(ARMS) of the matrices); a decision of a default solve counts
+    1.  The network then prefers an arm over the defaults where the arm was
+    clearly faster on matrices with similar features."""
+    adv = np.log(np.maximum(t_def, 1e-6) / np.maximum(t_run, 1e-6))
+    w = np.where(arm >= 0, len(ARMS) * np.exp(np.minimum(beta * adv, 8.0)), 1.0)
+    return w / len(ARMS)
+
+
 def _save(out, feats, bins, stats, runs):
     tmp = out + ".tmp.npz"
     np.savez_compressed(tmp, feat=np.concatenate(feats), bins=np.concatenate(bins), stats=np.concatenate(stats),
@@ -169,7 +236,10 @@ def sample_weights(stats, run, beta: float = 1.5):
     return w
 
 
-def train(data_files, out: str, epochs: int = 30, batch: int = 4096, lr: float = 2e-3, seed: int = 0):
+def train(data_files, out: str, epochs: int = 30, batch: int = 4096, lr: float = 2e-3, seed: int = 0,
+          beta: float = 3.0):
+    """Fit the network to per-decision data (``collect``) or per-run data
+    (``collect-run``, recognised by its per-solve times)."""
     import torch
 
     from . import binding
@@ -180,7 +250,11 @@ def train(data_files, out: str, epochs: int = 30, batch: int = 4096, lr: float =
     bins = np.concatenate([p["bins"] for p in parts])
     stats = np.concatenate([p["stats"] for p in parts])
     run = np.concatenate([p["run"] for p in parts])
-    w = sample_weights(stats, run)
+    if all("t_def" in p.files for p in parts):
+        w = run_weights(np.concatenate([p["t_def"] for p in parts]), np.concatenate([p["t_run"] for p in parts]),
+                        np.concatenate([p["arm"] for p in parts]), beta)
+    else:
+        w = sample_weights(stats, run)
     keep = w > 0
     log(f"[train] {len(w)} decisions, {keep.sum()} weighted, from {len(np.unique(run))} runs")
     X, B, W = feat[keep], bins[keep], w[keep]
@@ -223,8 +297,22 @@ def _init_theta(seed, mu, sd):
     return np.concatenate([np.asarray(p, dtype=np.float64).ravel() for p in parts])
 
 
-def evaluate(weights: str, start: int, count: int, lo: int, hi: int, min_conf: float, threads: int):
-    """Held-out matrices solved with the default rules and with the network."""
+def summarize(rows):
+    """Totals of an evaluation: default vs judged network time, overall and per family."""
+    tot_d = sum(r["t_default"] for r in rows)
+    tot_n = sum(r["t_judged"] for r in rows)
+    return {"matrices": len(rows), "total_default_s": tot_d, "total_net_s": tot_n,
+            "speedup": tot_d / tot_n if tot_n > 0 else None,
+            "per_family": {f: {"default_s": sum(r["t_default"] for r in rows if r["family"] == f),
+                               "net_s": sum(r["t_judged"] for r in rows if r["family"] == f)}
+                           for f in FAMILIES},
+            "all_ok": all(r["ok_net"] for r in rows)}
+
+
+def evaluate(weights: str, start: int, count: int, lo: int, hi: int, min_conf: float, threads: int,
+             out: str | None = None):
+    """Held-out matrices solved with the default rules and with the network;
+    with ``out`` the rows so far are saved every 10 matrices."""
     from . import binding
 
     binding.load_library()
@@ -251,17 +339,20 @@ def evaluate(weights: str, start: int, count: int, lo: int, hi: int, min_conf: f
                      "used": st["policy_used"], "fallback": st["policy_fallback"]})
         log(f"[eval] {i} {fam} n={n} default {t_def:.3f}s net {t_net:.3f}s ok={ok} "
             f"be {be_d / (n * EPS):.2f}/{be_n / (n * EPS):.2f} n eps")
+        if out and len(rows) % 10 == 0:
+            _save_eval(out, rows)
     binding.set_params(policy=0)
     binding.policy_set(None)
-    tot_d = sum(r["t_default"] for r in rows)
-    tot_n = sum(r["t_judged"] for r in rows)
-    summary = {"matrices": len(rows), "total_default_s": tot_d, "total_net_s": tot_n,
-               "speedup": tot_d / tot_n if tot_n > 0 else None,
-               "per_family": {f: {"default_s": sum(r["t_default"] for r in rows if r["family"] == f),
-                                  "net_s": sum(r["t_judged"] for r in rows if r["family"] == f)}
-                              for f in FAMILIES},
-               "all_ok": all(r["ok_net"] for r in rows)}
-    return summary, rows
+    if out:
+        _save_eval(out, rows)
+    return summarize(rows), rows
+
+
+def _save_eval(path: str, rows) -> None:
+    tmp = path + ".tmp"
+    with open(tmp, "w") as f:
+        json.dump({"summary": summarize(rows), "rows": rows}, f, indent=1)
+    os.replace(tmp, path)
 
 
 def main():
@@ -272,31 +363,36 @@ def main():
     c.add_argument("--count", type=int, default=100)
     c.add_argument("--out", required=True)
     c.add_argument("--seed", type=int, default=1)
+    cr = sub.add_parser("collect-run")
+    cr.add_argument("--start", type=int, default=0)
+    cr.add_argument("--count", type=int, default=100)
+    cr.add_argument("--out", required=True)
     t = sub.add_parser("train")
     t.add_argument("data", nargs="+")
     t.add_argument("--out", default=SAVED)
     t.add_argument("--epochs", type=int, default=30)
+    t.add_argument("--beta", type=float, default=3.0)
     e = sub.add_parser("evaluate")
     e.add_argument("--weights", default=SAVED)
     e.add_argument("--start", type=int, default=0)
     e.add_argument("--count", type=int, default=200)
     e.add_argument("--min-conf", type=float, default=0.0)
     e.add_argument("--out", default=None)
-    for p in (c, e):
+    for p in (c, cr, e):
         p.add_argument("--lo", type=int, default=1000)
         p.add_argument("--hi", type=int, default=8000)
         p.add_argument("--threads", type=int, default=8)
     args = ap.parse_args()
     if args.cmd == "collect":
         collect(args.start, args.count, args.out, args.lo, args.hi, args.seed, args.threads)
+    elif args.cmd == "collect-run":
+        collect_runs(args.start, args.count, args.out, args.lo, args.hi, args.threads)
     elif args.cmd == "train":
-        train(args.data, args.out, args.epochs)
+        train(args.data, args.out, args.epochs, beta=args.beta)
     else:
-        summary, rows = evaluate(args.weights, args.start, args.count, args.lo, args.hi, args.min_conf, args.threads)
+        summary, rows = evaluate(args.weights, args.start, args.count, args.lo, args.hi, args.min_conf, args.threads,
+                                 args.out)
         print(json.dumps(summary), flush=True)
-        if args.out:
-            with open(args.out, "w") as f:
-                json.dump({"summary": summary, "rows": rows}, f, indent=1)
 
 
 if __name__ == "__main__":

@@ -21,7 +21,7 @@ def test_header_declares_the_boundary():
     names = declared_functions()
     for required in ["neig_schur", "neig_schur_batched", "neig_sweep", "neig_aed", "neig_small_schur",
                      "neig_set_params", "neig_get_params", "neig_get_stats", "neig_finalize", "neig_version",
-                     "neig_set_batched_tune", "neig_get_batched_tune", "neig_reorder", "neig_policy_set",
+                     "neig_set_batched_tune", "neig_get_batched_tune", "neig_reorder", "neig_hessenberg", "neig_policy_set",
                      "neig_mlp_grad", "neig_mlp_infer"]:
         assert required in names
 
@@ -60,6 +60,13 @@ def test_argument_errors_without_gpu_work():
     assert lib.neig_schur(4, ctypes.c_void_p(8), 3, ctypes.c_void_p(8), 4, None, None, None) == -3
     assert lib.neig_schur(4, ctypes.c_void_p(8), 4, ctypes.c_void_p(8), 2, None, None, None) == -5
     assert lib.neig_schur(0, None, 1, None, 1, None, None, None) == 0
+    lib.neig_hessenberg.argtypes = [ctypes.c_int, ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p, ctypes.c_int,
+                                    ctypes.c_void_p]
+    assert lib.neig_hessenberg(-1, None, 1, None, 1, None) == -1
+    assert lib.neig_hessenberg(4, None, 4, None, 4, None) == -2
+    assert lib.neig_hessenberg(4, ctypes.c_void_p(8), 3, None, 4, None) == -3
+    assert lib.neig_hessenberg(4, ctypes.c_void_p(8), 4, ctypes.c_void_p(8), 3, None) == -5
+    assert lib.neig_hessenberg(0, None, 1, None, 1, None) == 0
 
 
 @pytest.mark.skipif(not os.path.exists(LIB), reason="libneig.so not built")

@@ -76,3 +76,18 @@ def test_autotune_candidate_filter():
 
     assert autotune._valid({"nw": 64, "ns": 32, "nmin": 96, "chase_w": 50})
     assert not autotune._valid({"nw": 64, "ns": 32, "nmin": 96, "chase_w": 49})
+
+
+def test_run_weights_rule():
+    from paper_2002_05024_amd import learn
+
+    k = len(learn.ARMS)
+    t_def = np.array([2.0, 2.0, 2.0, 1.0])
+    t_run = np.array([2.0, 1.0, 4.0, 1.0])
+    arm = np.array([0, 3, 5, -1])
+    w = learn.run_weights(t_def, t_run, arm, beta=1.0)
+    # an arm as fast as the defaults weighs as much as a default decision;
+    # twice as fast: twice as much; twice as slow: half
+    assert w[0] == pytest.approx(1.0) and w[3] == pytest.approx(1.0 / k)
+    assert w[1] == pytest.approx(2.0) and w[2] == pytest.approx(0.5)
+    assert len(set(learn.ARMS)) == k and learn.default_bins(5000) == (7, 5) and learn.default_bins(200) == (3, 3)
