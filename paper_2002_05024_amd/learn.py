@@ -18,8 +18,8 @@ Three stages, each run on a GPU:
              (backward error and orthogonality <= 50 n eps); a result that fails
              the check with the network is solved again with the default rules.
 
-Inputs are built on the host by worker threads while the GPU solves, so the
-GPU does not wait for them.
+Inputs are built on the host by worker threads in rounds between the timed
+solves (never during one).
 """
 from __future__ import annotations
 
@@ -61,28 +61,22 @@ def make_matrix(index: int, split: str, lo: int = 1000, hi: int = 8000):
 
 
 def producer(indices, split, lo, hi, threads=8, depth=None):
-    """Yield (index, family, H) in order, built ahead by worker threads."""
+    """Yield (index, family, H) in order.  Matrices are built in rounds of
+    ``depth`` by ``threads`` workers with single-threaded host BLAS, and a round
+    is handed out only when all of it is built: nothing runs on the host while
+    a solve is timed (the builders' host-memory traffic delays the solver's
+    small device-to-host read-backs and would show up in its time)."""
     from concurrent.futures import ThreadPoolExecutor
 
     from threadpoolctl import threadpool_limits
 
     depth = depth or 2 * threads
-    limits = threadpool_limits(limits=2)  # host BLAS threads per worker, for the whole run
-    ex = ThreadPoolExecutor(max_workers=threads)
-    futs = {}
-
-    def submit(k):
-        futs[k] = ex.submit(make_matrix, indices[k], split, lo, hi)
-
-    for k in range(min(depth, len(indices))):
-        submit(k)
-    for k in range(len(indices)):
-        fam, H = futs.pop(k).result()
-        if k + depth < len(indices):
-            submit(k + depth)
-        yield indices[k], fam, H
-    ex.shutdown()
-    limits.restore_original_limits()
+    for s0 in range(0, len(indices), depth):
+        chunk = indices[s0: s0 + depth]
+        with threadpool_limits(limits=1), ThreadPoolExecutor(max_workers=threads) as ex:
+            mats = list(ex.map(lambda i: make_matrix(i, split, lo, hi), chunk))
+        for i, (fam, H) in zip(chunk, mats):
+            yield i, fam, H
 
 
 class Solver:
@@ -204,15 +198,22 @@ def _save_runs(out, rec):
     os.replace(tmp, out)
 
 
-def run_weights(t_def, t_run, arm, beta: float = 3.0):
-    """Weights of the per-run data: a decision of an arm's solve counts
+def run_weights(t_def, t_run, arm, beta: float = 3.0, run=None):
+    """Weights of the per-run data: an arm's solve counts
     exp(beta * log(t_default / t_arm)) times the number of arms (each arm is
-    tried on 1/len(ARMS) of the matrices); a decision of a default solve counts
-    1.  The network then prefers an arm over the defaults where the arm was
-    clearly faster on matrices with similar features."""
+    tried on 1/len(ARMS) of the matrices); a default solve counts 1.  With
+    ``run`` (one id per solve's decisions; the default and the arm solve of a
+    matrix have the same id but different ``arm``) a solve's weight is spread
+    evenly over its decisions, so that a solve with more decisions does not
+    count more.  The network then prefers an arm over the defaults where the
+    arm was clearly faster on matrices with similar features."""
     adv = np.log(np.maximum(t_def, 1e-6) / np.maximum(t_run, 1e-6))
-    w = np.where(arm >= 0, len(ARMS) * np.exp(np.minimum(beta * adv, 8.0)), 1.0)
-    return w / len(ARMS)
+    w = np.where(arm >= 0, len(ARMS) * np.exp(np.minimum(beta * adv, 8.0)), 1.0) / len(ARMS)
+    if run is not None:
+        key = np.asarray(run, dtype=np.int64) * 64 + (np.asarray(arm) + 1)
+        _, inv, cnt = np.unique(key, return_inverse=True, return_counts=True)
+        w = w / cnt[inv] * cnt.mean()
+    return w
 
 
 def _save(out, feats, bins, stats, runs):
@@ -252,7 +253,7 @@ def train(data_files, out: str, epochs: int = 30, batch: int = 4096, lr: float =
     run = np.concatenate([p["run"] for p in parts])
     if all("t_def" in p.files for p in parts):
         w = run_weights(np.concatenate([p["t_def"] for p in parts]), np.concatenate([p["t_run"] for p in parts]),
-                        np.concatenate([p["arm"] for p in parts]), beta)
+                        np.concatenate([p["arm"] for p in parts]), beta, run)
     else:
         w = sample_weights(stats, run)
     keep = w > 0
@@ -372,6 +373,7 @@ def main():
     t.add_argument("--out", default=SAVED)
     t.add_argument("--epochs", type=int, default=30)
     t.add_argument("--beta", type=float, default=3.0)
+    t.add_argument("--batch", type=int, default=4096)
     e = sub.add_parser("evaluate")
     e.add_argument("--weights", default=SAVED)
     e.add_argument("--start", type=int, default=0)
@@ -388,7 +390,7 @@ def main():
     elif args.cmd == "collect-run":
         collect_runs(args.start, args.count, args.out, args.lo, args.hi, args.threads)
     elif args.cmd == "train":
-        train(args.data, args.out, args.epochs, beta=args.beta)
+        train(args.data, args.out, args.epochs, batch=args.batch, beta=args.beta)
     else:
         summary, rows = evaluate(args.weights, args.start, args.count, args.lo, args.hi, args.min_conf, args.threads,
                                  args.out)

@@ -91,3 +91,19 @@ def test_run_weights_rule():
     assert w[0] == pytest.approx(1.0) and w[3] == pytest.approx(1.0 / k)
     assert w[1] == pytest.approx(2.0) and w[2] == pytest.approx(0.5)
     assert len(set(learn.ARMS)) == k and learn.default_bins(5000) == (7, 5) and learn.default_bins(200) == (3, 3)
+
+
+def test_run_weights_spread_over_decisions():
+    from paper_2002_05024_amd import learn
+
+    # matrix 0: default solve with 1 decision, arm solve with 3; matrix 1: 2 + 2
+    t_def = np.array([1.0, 1.0, 1.0, 1.0, 1.0, 1.0, 1.0, 1.0])
+    t_run = np.array([1.0, 0.5, 0.5, 0.5, 1.0, 1.0, 1.0, 1.0])
+    arm = np.array([-1, 2, 2, 2, -1, -1, 4, 4])
+    run = np.array([0, 0, 0, 0, 1, 1, 1, 1])
+    w = learn.run_weights(t_def, t_run, arm, beta=1.0, run=run)
+    k = len(learn.ARMS)
+    scale = 2.0  # mean decisions per solve
+    assert w[0] == pytest.approx(scale / k)
+    assert np.allclose(w[1:4], 2.0 / 3 * scale)  # a solve's weight split over its decisions
+    assert np.allclose(w[4:6], 0.5 / k * scale) and np.allclose(w[6:8], 0.5 * scale)
