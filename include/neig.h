@@ -58,7 +58,10 @@ typedef struct neig_params {
                          decision logged for neig_policy_log;
                       3: fixed bins for the whole call, shift bin seed mod 8 and window
                          bin (seed / 8) mod 8, every decision logged (per-run
-                         exploration)                                                     */
+                         exploration);
+                      4: per-matrix proposal: the network's bins at the first decision
+                         hold for the whole call (the default rules when no network is
+                         installed or it is not confident); that decision is logged   */
     int seed;      /* seed of the exploration generator                                  */
     int reserved[4];
 } neig_params;
@@ -288,7 +291,7 @@ int neig_policy_set(const float *theta, int nparam, float min_conf);
 
 /*
  * neig_policy_log -- the decisions of the most recent neig_schur call with
- * policy 1, 2 or 3.  For decision i < min(count, cap): feat[24 i ..] its features,
+ * policy 1, 2, 3 or 4.  For decision i < min(count, cap): feat[24 i ..] its features,
  * bins[2 i ..] the (shift, window) bins applied (or proposed, when the default
  * rules decided), stats[4 i ..] = deflations of the next window, milliseconds
  * from the decision to the end of that window, the order m of the active

@@ -39,31 +39,27 @@ __device__ __forceinline__ neig_d4 mfma16(double a, double b, neig_d4 c) {
     return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
 }
 
-extern "C" __global__ void __launch_bounds__(UPD_THREADS)
-k_update(UpdArgs args) {
-    extern __shared__ double lds[];
-    int ti = 0;
-    const int bid = blockIdx.x;
-    while (ti + 1 < args.ntask && args.t[ti + 1].tile0 <= bid) ++ti;
-    const UpdTask T = args.t[ti];
-    const int tile = bid - T.tile0;
+// The body for a window of NRT 16-row tiles (w <= 16 NRT): every loop has a
+// compile-time trip count, so the matrix-core instructions issue back to back
+// with no branch between them (the zero padding of U^T and of the staged strip
+// makes the extra k-steps harmless).
+template <int NRT>
+__device__ __forceinline__ void upd_body(const UpdTask &T, int tile, double *lds) {
     const int lane = threadIdx.x & 63;
     const int q = threadIdx.x >> 6;
     const int w = T.w;
-    const int wp = (w + 15) & ~15;
-    const int kp = (w + 3) & ~3;
-    const int nrt = wp >> 4;
+    constexpr int wp = 16 * NRT;
     const int li = lane & 15, lk = lane >> 4;
-    const int ldus = wp + 1;
+    constexpr int ldus = wp + 1;
     double *Us = lds;                       // U^T, wp x wp (zero padded), leading dimension ldus
     double *Cs = lds + (size_t)wp * ldus;   // side 0: the strip's slice
-    neig_d4 acc[8];
+    neig_d4 acc[NRT];
 #pragma unroll
-    for (int r = 0; r < 8; ++r) acc[r] = (neig_d4){0.0, 0.0, 0.0, 0.0};
+    for (int r = 0; r < NRT; ++r) acc[r] = (neig_d4){0.0, 0.0, 0.0, 0.0};
 
     if (T.side == 0) {
         const int c0 = tile * UPD_SLICE;
-        const int ldcs = wp + 1;
+        constexpr int ldcs = wp + 1;
         for (int idx = threadIdx.x; idx < wp * UPD_SLICE; idx += UPD_THREADS) {
             const int r = idx % wp, c = idx / wp;
             double v = 0.0;
@@ -76,24 +72,21 @@ k_update(UpdArgs args) {
         }
         __syncthreads();
         const int cb = 16 * q + li;
-        for (int k = 0; k < kp; k += 4) {
+#pragma unroll 4
+        for (int k = 0; k < wp; k += 4) {
             const int kk = k + lk;
             const double b = Cs[kk + cb * ldcs];
 #pragma unroll
-            for (int rt = 0; rt < 8; ++rt) {
-                if (rt < nrt) acc[rt] = mfma16(Us[(16 * rt + li) + kk * ldus], b, acc[rt]);
-            }
+            for (int rt = 0; rt < NRT; ++rt) acc[rt] = mfma16(Us[(16 * rt + li) + kk * ldus], b, acc[rt]);
         }
         const int col = c0 + 16 * q + li;
         if (col < T.len) {
 #pragma unroll
-            for (int rt = 0; rt < 8; ++rt) {
-                if (rt < nrt) {
+            for (int rt = 0; rt < NRT; ++rt) {
 #pragma unroll
-                    for (int r = 0; r < 4; ++r) {
-                        const int row = 16 * rt + lk + 4 * r;
-                        if (row < w) AT(T.C, T.ldc, row, col) = acc[rt][r];
-                    }
+                for (int r = 0; r < 4; ++r) {
+                    const int row = 16 * rt + lk + 4 * r;
+                    if (row < w) AT(T.C, T.ldc, row, col) = acc[rt][r];
                 }
             }
         }
@@ -102,11 +95,11 @@ k_update(UpdArgs args) {
         // together), then U^T from LDS
         const int rbase = tile * UPD_SLICE + 16 * q;
         const int arow = rbase + li;
-        double areg[UPD_WMAX / 4];
+        double areg[4 * NRT];
 #pragma unroll
-        for (int s4 = 0; s4 < UPD_WMAX / 4; ++s4) {
+        for (int s4 = 0; s4 < 4 * NRT; ++s4) {
             const int kk = 4 * s4 + lk;
-            areg[s4] = (4 * s4 < kp && arow < T.len && kk < w) ? AT(T.C, T.ldc, arow, kk) : 0.0;
+            areg[s4] = (arow < T.len && kk < w) ? AT(T.C, T.ldc, arow, kk) : 0.0;
         }
         for (int idx = threadIdx.x; idx < wp * wp; idx += UPD_THREADS) {
             const int r = idx % wp, k = idx / wp;
@@ -114,27 +107,41 @@ k_update(UpdArgs args) {
         }
         __syncthreads();
 #pragma unroll
-        for (int s4 = 0; s4 < UPD_WMAX / 4; ++s4) {
-            if (4 * s4 < kp) {
-                const int kk = 4 * s4 + lk;
+        for (int s4 = 0; s4 < 4 * NRT; ++s4) {
+            const int kk = 4 * s4 + lk;
 #pragma unroll
-                for (int ct = 0; ct < 8; ++ct) {
-                    if (ct < nrt) acc[ct] = mfma16(areg[s4], Us[(16 * ct + li) + kk * ldus], acc[ct]);
+            for (int ct = 0; ct < NRT; ++ct) acc[ct] = mfma16(areg[s4], Us[(16 * ct + li) + kk * ldus], acc[ct]);
+        }
+#pragma unroll
+        for (int ct = 0; ct < NRT; ++ct) {
+            const int col = 16 * ct + li;
+            if (col < w) {
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int row = rbase + lk + 4 * r;
+                    if (row < T.len) AT(T.C, T.ldc, row, col) = acc[ct][r];
                 }
             }
         }
-#pragma unroll
-        for (int ct = 0; ct < 8; ++ct) {
-            if (ct < nrt) {
-                const int col = 16 * ct + li;
-                if (col < w) {
-#pragma unroll
-                    for (int r = 0; r < 4; ++r) {
-                        const int row = rbase + lk + 4 * r;
-                        if (row < T.len) AT(T.C, T.ldc, row, col) = acc[ct][r];
-                    }
-                }
-            }
-        }
+    }
+}
+
+extern "C" __global__ void __launch_bounds__(UPD_THREADS)
+k_update(UpdArgs args) {
+    extern __shared__ double lds[];
+    int ti = 0;
+    const int bid = blockIdx.x;
+    while (ti + 1 < args.ntask && args.t[ti + 1].tile0 <= bid) ++ti;
+    const UpdTask T = args.t[ti];
+    const int tile = bid - T.tile0;
+    switch ((T.w + 15) >> 4) {  // uniform per workgroup
+        case 1: upd_body<1>(T, tile, lds); break;
+        case 2: upd_body<2>(T, tile, lds); break;
+        case 3: upd_body<3>(T, tile, lds); break;
+        case 4: upd_body<4>(T, tile, lds); break;
+        case 5: upd_body<5>(T, tile, lds); break;
+        case 6: upd_body<6>(T, tile, lds); break;
+        case 7: upd_body<7>(T, tile, lds); break;
+        default: upd_body<8>(T, tile, lds); break;
     }
 }

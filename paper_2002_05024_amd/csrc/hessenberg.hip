@@ -77,6 +77,34 @@ __device__ __forceinline__ double hrd_transpose_sum(double (&x)[HRD_NB], int lan
     return x[0];
 }
 
+// Column sums over the workgroups' partials (nblk rows of stride HRD_NB + 2)
+// for the first 64 entries, by all 256 threads: thread (c, q) adds the blocks
+// q, q + 4, ... in order, then the four quarter sums are added in order; the
+// totals land in out[0..63].  The order is fixed, so results are reproducible.
+__device__ __forceinline__ void hrd_sum_partials(const double *part, int nblk, double (*red)[HRD_NB],
+                                                 double *out) {
+    const int t = threadIdx.x, c = t & 63, q = t >> 6;
+    double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+    int b = q;
+    for (; b + 12 < nblk; b += 16) {
+        a0 += part[(size_t)b * (HRD_NB + 2) + c];
+        a1 += part[(size_t)(b + 4) * (HRD_NB + 2) + c];
+        a2 += part[(size_t)(b + 8) * (HRD_NB + 2) + c];
+        a3 += part[(size_t)(b + 12) * (HRD_NB + 2) + c];
+    }
+    for (; b < nblk; b += 4) a0 += part[(size_t)b * (HRD_NB + 2) + c];
+    red[q][c] = (a0 + a1) + (a2 + a3);
+    __syncthreads();
+    if (t < HRD_NB) out[t] = (red[0][t] + red[1][t]) + (red[2][t] + red[3][t]);
+    __syncthreads();
+}
+
+// Stage the panel's T (HRD_NB x HRD_NB) in LDS.
+__device__ __forceinline__ void hrd_stage_t(const double *T, double *Ts) {
+    for (int idx = threadIdx.x; idx < HRD_NB * HRD_NB; idx += HRD_THREADS) Ts[idx] = T[idx];
+    __syncthreads();
+}
+
 // (scale, ssq) representation of a sum of squares: value = scale^2 * ssq.
 __device__ __forceinline__ void hrd_ssq_merge(double &sc, double &sq, double sc2, double sq2) {
     if (sc2 == 0.0) return;
@@ -109,37 +137,50 @@ extern "C" __global__ void __launch_bounds__(HRD_THREADS) k_hrd_a(HrdArgs p) {
         uprev[t] = p.st->u[t];
     }
     __syncthreads();
-    double vnew = 0.0, ycol = 0.0;
-    if (in) {
-        // reflector i-1: its vector, its column of H, its column of Y
-        const double scal = p.st->scal, tau = p.st->tau, beta = p.st->beta;
-        const double old = AT(p.A, p.lda, g, j - 1);
-        vnew = r < i - 1 ? 0.0 : (r == i - 1 ? 1.0 : old * scal);
-        AT(p.V, p.ldw, r, i - 1) = vnew;
-        if (r >= i - 1) AT(p.A, p.lda, g, j - 1) = (r == i - 1) ? beta : 0.0;
-        double y = AT(p.A, p.lda, g, j);
-        for (int ch = 0; ch < p.nch; ++ch) y += p.zpart[(size_t)ch * p.ldw + r];
-        double acc = 0.0;
-        for (int c = 0; c < i - 1; ++c) acc = fma(AT(p.Y, p.ldw, g, c), uprev[c], acc);
-        ycol = tau * (y - acc);
-        AT(p.Y, p.ldw, g, i - 1) = ycol;
-    }
-    if (i == p.jb) return;  // the panel's last finishing launch
+    const bool last = i == p.jb;  // the panel's last launch only finishes reflector i-1
     double x[HRD_NB];
 #pragma unroll
     for (int c = 0; c < HRD_NB; ++c) x[c] = 0.0;
     if (in) {
-        // right: a -= Y(g, 0:i) V(i-1, 0:i)^T   (V(i-1, i-1) = 1)
-        double acc = ycol;
-        for (int c = 0; c < i - 1; ++c) acc = fma(AT(p.Y, p.ldw, g, c), vrow[c], acc);
-        const double a = AT(p.A, p.lda, g, j) - acc;
-        AT(p.A, p.lda, g, j) = a;
+        // reflector i-1: its vector, its column of H, its column of Y; with one
+        // pass over Y(g, 0:i-1) both Y u and the right update Y V(i-1, :)^T
+        const double scal = p.st->scal, tau = p.st->tau, beta = p.st->beta;
+        const double old = AT(p.A, p.lda, g, j - 1);
+        const double vnew = r < i - 1 ? 0.0 : (r == i - 1 ? 1.0 : old * scal);
+        AT(p.V, p.ldw, r, i - 1) = vnew;
+        if (r >= i - 1) AT(p.A, p.lda, g, j - 1) = (r == i - 1) ? beta : 0.0;
+        const double aj = AT(p.A, p.lda, g, j);  // column j, not yet touched by this panel
+        // the GEMV partials, eight loads in flight, added in a fixed order
+        double z[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+        int ch = 0;
+        for (; ch + 8 <= p.nch; ch += 8) {
+            const double *zp = p.zpart + (size_t)ch * p.ldw + r;
 #pragma unroll
-        for (int c = 0; c < HRD_NB; ++c) {
-            if (c < i - 1) x[c] = AT(p.V, p.ldw, r, c) * a;
-            else if (c == i - 1) x[c] = vnew * a;
+            for (int u = 0; u < 8; ++u) z[u] += zp[u * (size_t)p.ldw];
+        }
+        for (; ch < p.nch; ++ch) z[0] += p.zpart[(size_t)ch * p.ldw + r];
+        const double y = aj + (((z[0] + z[1]) + (z[2] + z[3])) + ((z[4] + z[5]) + (z[6] + z[7])));
+        double yu = 0.0, yv = 0.0;
+#pragma unroll 8
+        for (int c = 0; c < i - 1; ++c) {
+            const double yc = AT(p.Y, p.ldw, g, c);
+            yu = fma(yc, uprev[c], yu);
+            yv = fma(yc, vrow[c], yv);
+        }
+        const double ycol = tau * (y - yu);
+        AT(p.Y, p.ldw, g, i - 1) = ycol;
+        if (!last) {
+            // right: a -= Y(g, 0:i) V(i-1, 0:i)^T   (V(i-1, i-1) = 1)
+            const double a = aj - (yv + ycol);
+            AT(p.A, p.lda, g, j) = a;
+#pragma unroll
+            for (int c = 0; c < HRD_NB; ++c) {
+                if (c < i - 1) x[c] = AT(p.V, p.ldw, r, c) * a;
+                else if (c == i - 1) x[c] = vnew * a;
+            }
         }
     }
+    if (last) return;
     const double ws = hrd_transpose_sum(x, lane);
     red[wv][lane] = ws;
     __syncthreads();
@@ -155,16 +196,14 @@ extern "C" __global__ void __launch_bounds__(HRD_THREADS) k_hrd_a(HrdArgs p) {
     __syncthreads();
     if (!is_last) return;
     __threadfence();
-    if (t < HRD_NB) {
-        double w = 0.0;
-        for (int b = 0; b < (int)gridDim.x; ++b) w += p.part[(size_t)b * (HRD_NB + 2) + t];
-        red[0][t] = w;
-    }
-    __syncthreads();
+    __shared__ double Ts[HRD_NB * HRD_NB];
+    __shared__ double wsum[HRD_NB];
+    hrd_sum_partials(p.part, gridDim.x, red, wsum);
+    hrd_stage_t(p.T, Ts);
     if (t < i) {
         // s = T^T w, T upper triangular
         double s = 0.0;
-        for (int c = 0; c <= t; ++c) s = fma(p.T[c + (size_t)t * HRD_NB], red[0][c], s);
+        for (int c = 0; c <= t; ++c) s = fma(Ts[c + t * HRD_NB], wsum[c], s);
         p.st->s[t] = s;
     }
     if (t == 0) p.st->count_a = 0;
@@ -192,10 +231,16 @@ extern "C" __global__ void __launch_bounds__(HRD_THREADS) k_hrd_b(HrdArgs p) {
     for (int c = 0; c < HRD_NB; ++c) x[c] = 0.0;
     double sc = 0.0, sq = 0.0;
     if (in) {
+        // the row of V is read once: held in x, then replaced by V(r, c) a
         double a = AT(p.A, p.lda, g, j);
         if (i > 0) {
+#pragma unroll
+            for (int c = 0; c < HRD_NB; ++c)
+                if (c < i) x[c] = AT(p.V, p.ldw, r, c);
             double acc = 0.0;
-            for (int c = 0; c < i; ++c) acc = fma(AT(p.V, p.ldw, r, c), s[c], acc);
+#pragma unroll
+            for (int c = 0; c < HRD_NB; ++c)
+                if (c < i) acc = fma(x[c], s[c], acc);
             a -= acc;
             AT(p.A, p.lda, g, j) = a;
         }
@@ -205,8 +250,10 @@ extern "C" __global__ void __launch_bounds__(HRD_THREADS) k_hrd_b(HrdArgs p) {
                 sq = 1.0;
             }
 #pragma unroll
-            for (int c = 0; c < HRD_NB; ++c)
-                if (c < i) x[c] = AT(p.V, p.ldw, r, c) * a;
+            for (int c = 0; c < HRD_NB; ++c) x[c] *= a;
+        } else {
+#pragma unroll
+            for (int c = 0; c < HRD_NB; ++c) x[c] = 0.0;
         }
     }
     const double us = hrd_transpose_sum(x, lane);
@@ -242,12 +289,29 @@ extern "C" __global__ void __launch_bounds__(HRD_THREADS) k_hrd_b(HrdArgs p) {
     __threadfence();
     __shared__ double coef[2];
     __shared__ double ufin[HRD_NB];
-    if (t == 0) {
+    __shared__ double usum[HRD_NB];
+    __shared__ double Ts[HRD_NB * HRD_NB];
+    hrd_sum_partials(p.part, gridDim.x, red, usum);
+    hrd_stage_t(p.T, Ts);
+    if (t < 64) {
+        // the tail's scaled sum of squares: lane l merges blocks l, l + 64, ...
+        // in order, then the lanes merge by a fixed butterfly
         double a = 0.0, b = 0.0;
-        for (int q = 0; q < (int)gridDim.x; ++q) {
+        for (int q = t; q < (int)gridDim.x; q += 64) {
             const double *pq = p.part + (size_t)q * (HRD_NB + 2);
             hrd_ssq_merge(a, b, pq[HRD_NB], pq[HRD_NB + 1]);
         }
+#pragma unroll
+        for (int o = 32; o >= 1; o >>= 1) {
+            const double a2 = __shfl_xor(a, o), b2 = __shfl_xor(b, o);
+            hrd_ssq_merge(a, b, a2, b2);
+        }
+        rsc[0] = a;   // every lane holds the same merged pair
+        rsq[0] = b;
+    }
+    __syncthreads();
+    if (t == 0) {
+        const double a = rsc[0], b = rsq[0];
         const double sigma = a * sqrt(b);
         const double alpha = AT(p.A, p.lda, (size_t)p.k0 + 1 + i, j);
         double beta = alpha, tau = 0.0, scal = 0.0;
@@ -266,9 +330,7 @@ extern "C" __global__ void __launch_bounds__(HRD_THREADS) k_hrd_b(HrdArgs p) {
     }
     __syncthreads();
     if (t < i) {
-        double v = 0.0;
-        for (int q = 0; q < (int)gridDim.x; ++q) v += p.part[(size_t)q * (HRD_NB + 2) + t];
-        const double u = AT(p.V, p.ldw, i, t) + coef[1] * v;
+        const double u = AT(p.V, p.ldw, i, t) + coef[1] * usum[t];
         ufin[t] = u;
         p.st->u[t] = u;
     }
@@ -277,7 +339,7 @@ extern "C" __global__ void __launch_bounds__(HRD_THREADS) k_hrd_b(HrdArgs p) {
         // column i of T: T(0:i, i) = -tau T(0:i, 0:i) u, T(i, i) = tau, zero below
         double v = 0.0;
         if (t < i) {
-            for (int c = t; c < i; ++c) v = fma(p.T[t + (size_t)c * HRD_NB], ufin[c], v);
+            for (int c = t; c < i; ++c) v = fma(Ts[t + c * HRD_NB], ufin[c], v);
             v *= -coef[0];
         } else if (t == i) {
             v = coef[0];
@@ -304,13 +366,22 @@ extern "C" __global__ void __launch_bounds__(HRD_THREADS) k_hrd_gemv(HrdArgs p) 
     double a0 = 0.0, a1 = 0.0, b0 = 0.0, b1 = 0.0;
     int c = 0;
     if (in1) {
-        for (; c + 2 <= cn; c += 2) {
+        // eight independent loads in flight per lane before their first use
+        for (; c + 4 <= cn; c += 4) {
             const double *c1 = col + (size_t)c * p.lda;
-            const double *c2 = c1 + p.lda;
-            a0 = fma(c1[r0], v[c], a0);
-            a1 = fma(c1[r1], v[c], a1);
-            b0 = fma(c2[r0], v[c + 1], b0);
-            b1 = fma(c2[r1], v[c + 1], b1);
+            const size_t ld = (size_t)p.lda;
+            const double x00 = c1[r0], x01 = c1[r1];
+            const double x10 = c1[ld + r0], x11 = c1[ld + r1];
+            const double x20 = c1[2 * ld + r0], x21 = c1[2 * ld + r1];
+            const double x30 = c1[3 * ld + r0], x31 = c1[3 * ld + r1];
+            a0 = fma(x00, v[c], a0);
+            a1 = fma(x01, v[c], a1);
+            b0 = fma(x10, v[c + 1], b0);
+            b1 = fma(x11, v[c + 1], b1);
+            a0 = fma(x20, v[c + 2], a0);
+            a1 = fma(x21, v[c + 2], a1);
+            b0 = fma(x30, v[c + 3], b0);
+            b1 = fma(x31, v[c + 3], b1);
         }
         for (; c < cn; ++c) {
             const double *c1 = col + (size_t)c * p.lda;
@@ -347,10 +418,13 @@ __device__ __forceinline__ neig_d4 hrd_mfma(double a, double b, neig_d4 c) {
 }
 
 // P_s(i, c) = sum over k in split s of op(C)(i, k) V(k, c): 64 output rows per
-// workgroup, K in 32-wide LDS-staged steps, four waves of 16 rows each.
+// workgroup, K in 32-wide LDS-staged steps, four waves of 16 rows each; the
+// next step's operands are loaded into registers while the matrix cores work
+// on the current one.
 // Operand layouts of v_mfma_f64_16x16x4_f64 (lane l): A(l%16, l/16),
 // B(l/16, l%16); accumulator double r of lane l holds D(l/16 + 4r, l%16).
-extern "C" __global__ void __launch_bounds__(HRD_THREADS) k_hrd_skinny(SkArgs p) {
+template <int TRANS>
+__device__ __forceinline__ void hrd_skinny_body(const SkArgs &p) {
     __shared__ double Cs[64 * HRD_PAD];
     __shared__ double Vs[64 * HRD_PAD];
     const int t = threadIdx.x, lane = t & 63, q = t >> 6;
@@ -362,30 +436,47 @@ extern "C" __global__ void __launch_bounds__(HRD_THREADS) k_hrd_skinny(SkArgs p)
 #pragma unroll
     for (int ct = 0; ct < 4; ++ct) acc[ct] = (neig_d4){0.0, 0.0, 0.0, 0.0};
     const int nct = (p.nbc + 15) >> 4;
-    for (int kb = ks; kb < ke; kb += 32) {
-        for (int idx = t; idx < 64 * 32; idx += HRD_THREADS) {
+    double rc[8], rv[8];
+    auto fetch = [&](int kb) {
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int idx = t + u * HRD_THREADS;
             int ii, kk;
-            double v = 0.0;
-            if (p.trans == 0) {
+            if (TRANS == 0) {
                 ii = idx & 63;
                 kk = idx >> 6;
-                if (i0 + ii < p.M && kb + kk < ke) v = AT(p.C, p.ldc, i0 + ii, kb + kk);
+                rc[u] = (i0 + ii < p.M && kb + kk < ke) ? AT(p.C, p.ldc, i0 + ii, kb + kk) : 0.0;
             } else {
                 kk = idx & 31;
                 ii = idx >> 5;
-                if (i0 + ii < p.M && kb + kk < ke) v = AT(p.C, p.ldc, kb + kk, i0 + ii);
+                rc[u] = (i0 + ii < p.M && kb + kk < ke) ? AT(p.C, p.ldc, kb + kk, i0 + ii) : 0.0;
             }
-            Cs[ii * HRD_PAD + kk] = v;
             const int vk = idx & 31, vc = idx >> 5;
-            Vs[vc * HRD_PAD + vk] = (vc < p.nbc && kb + vk < ke) ? AT(p.V, p.ldv, kb + vk, vc) : 0.0;
+            rv[u] = (vc < p.nbc && kb + vk < ke) ? AT(p.V, p.ldv, kb + vk, vc) : 0.0;
         }
+    };
+    auto store = [&]() {
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int idx = t + u * HRD_THREADS;
+            const int ii = TRANS == 0 ? (idx & 63) : (idx >> 5);
+            const int kk = TRANS == 0 ? (idx >> 6) : (idx & 31);
+            Cs[ii * HRD_PAD + kk] = rc[u];
+            Vs[(idx >> 5) * HRD_PAD + (idx & 31)] = rv[u];
+        }
+    };
+    if (ks < ke) fetch(ks);
+    for (int kb = ks; kb < ke; kb += 32) {
+        store();
         __syncthreads();
+        if (kb + 32 < ke) fetch(kb + 32);
 #pragma unroll
         for (int k4 = 0; k4 < 32; k4 += 4) {
             const double a = Cs[(16 * q + li) * HRD_PAD + k4 + lk];
+            // all four column tiles (V is zero beyond nbc): no runtime branch
+            // between the matrix-core instructions
 #pragma unroll
-            for (int ct = 0; ct < 4; ++ct)
-                if (ct < nct) acc[ct] = hrd_mfma(a, Vs[(16 * ct + li) * HRD_PAD + k4 + lk], acc[ct]);
+            for (int ct = 0; ct < 4; ++ct) acc[ct] = hrd_mfma(a, Vs[(16 * ct + li) * HRD_PAD + k4 + lk], acc[ct]);
         }
         __syncthreads();
     }
@@ -402,6 +493,9 @@ extern "C" __global__ void __launch_bounds__(HRD_THREADS) k_hrd_skinny(SkArgs p)
         }
     }
 }
+
+extern "C" __global__ void __launch_bounds__(HRD_THREADS) k_hrd_skinny_n(SkArgs p) { hrd_skinny_body<0>(p); }
+extern "C" __global__ void __launch_bounds__(HRD_THREADS) k_hrd_skinny_t(SkArgs p) { hrd_skinny_body<1>(p); }
 
 struct RdArgs {
     const double *P;   // ns partials of M x nbc (leading dimension M), stride sp

@@ -669,6 +669,8 @@ class Solver {
         rng_state_ = 0x243f6a8885a308d3ull ^ (uint64_t)(unsigned)p_.seed;
         policy_log_.clear();
         int nw_next = 0, ns_next = 0;
+        bool held_set = false;
+        int held_used = 0, held_bins[2] = {0, 0};
         PolicySample pending;
         bool have_pending = false;
         double t_decide = 0.0;
@@ -705,7 +707,16 @@ class Solver {
             ndefl = (nd > 0) ? 0 : ndefl + 1;
             const int m2 = kbot - ktop + 1;
             if (m2 <= nmin_) continue;
-            if (mode != 0) {
+            if (mode == 4 && held_set) {
+                // per-matrix proposal: the bins of the first decision hold
+                if (held_used) {
+                    ns_next = kNsBins[held_bins[0]];
+                    nw_next = kNwBins[held_bins[1]];
+                    stats_.policy_used++;
+                } else {
+                    stats_.policy_fallback++;
+                }
+            } else if (mode != 0) {
                 t_decide = now_ms();
                 Decision d = propose(ktop, kbot, ritz, nd, nw);
                 int bns = d.bins[0], bnw = d.bins[1];
@@ -736,6 +747,12 @@ class Solver {
                 pending.m = (float)m2;
                 pending.used_net = used;
                 have_pending = true;
+                if (mode == 4) {
+                    held_set = true;
+                    held_used = used;
+                    held_bins[0] = bns;
+                    held_bins[1] = bnw;
+                }
             }
             if (nd > 0 && 100 * nd > nibble_ * nw) continue;
             int ns = default_ns(m2);
@@ -903,18 +920,22 @@ class Solver {
 
 // Thin product out = (sum over splits of op(C) V - X B) T (X, T optional) with
 // op(C) M x K, V K x nbc; the long dimension K is split so that the launch has
-// about two workgroups per compute unit.
+// about two workgroups per compute unit, but into at most 64 parts (the
+// partials are summed by one workgroup per 64 rows).
 void hrd_thin(DeviceWs &ws, double *sk, const double *C, int ldc, int trans, int M, int K, const double *V,
               int ldv, int nbc, const double *X, int ldx, const double *B, const double *T, double *out, int ldo,
               hipStream_t s) {
     if (M <= 0) return;
     const int rb = (M + 63) / 64;
-    int nsplit = std::max(1, std::min((2 * ws.cus + rb - 1) / rb, (K + 31) / 32));
+    int nsplit = std::max(1, std::min({(2 * ws.cus + rb - 1) / rb, (K + 31) / 32, 64}));
     const int kper = ((K + nsplit - 1) / nsplit + 31) / 32 * 32;
     nsplit = (K + kper - 1) / kper;
     const size_t sp = (size_t)M * nbc;
     SkArgs a{C, V, sk, sp, ldc, ldv, M, K, nbc, kper, trans};
-    hipLaunchKernelGGL(k_hrd_skinny, dim3(rb, nsplit), dim3(HRD_THREADS), 0, s, a);
+    if (trans)
+        hipLaunchKernelGGL(k_hrd_skinny_t, dim3(rb, nsplit), dim3(HRD_THREADS), 0, s, a);
+    else
+        hipLaunchKernelGGL(k_hrd_skinny_n, dim3(rb, nsplit), dim3(HRD_THREADS), 0, s, a);
     RdArgs r{sk, sp, nsplit, X, ldx, B, T, out, ldo, M, nbc};
     hipLaunchKernelGGL(k_hrd_reduce, dim3(rb), dim3(HRD_THREADS), 0, s, r);
 }
@@ -1381,7 +1402,7 @@ extern "C" int neig_set_params(const neig_params *p) {
     if (p->nibble < 0 || p->nibble > 100) return -8;
     if (p->exc < 0) return -9;
     if (p->timing < 0 || p->timing > 1) return -10;
-    if (p->policy < 0 || p->policy > 3) return -11;
+    if (p->policy < 0 || p->policy > 4) return -11;
     std::lock_guard<std::mutex> lock(g_mutex);
     g_params = *p;
     return 0;

@@ -35,6 +35,7 @@ import numpy as np
 HERE = os.path.dirname(os.path.abspath(__file__))
 SAVED = os.path.join(HERE, "policy_gfx950.npy")
 FAMILIES = ("random", "prescribed", "graded")
+POLICY = 4  # how the committed network is used: one proposal per matrix
 EPS = 2.0 ** -52
 
 
@@ -147,6 +148,8 @@ def collect(start: int, count: int, out: str, lo: int, hi: int, seed: int, threa
 # = 48, 64, 80, 96 rows (the default rules use 32 shifts and a 64-row window
 # for active blocks of 300 rows or more).
 ARMS = [(a, b) for a in (3, 5, 7) for b in (3, 5, 6, 7)]
+# the arms that the first round of exploration found competitive somewhere
+FOCUSED_ARMS = [(7, 3), (5, 3), (5, 5), (7, 6)]
 
 
 def default_bins(m):
@@ -154,7 +157,7 @@ def default_bins(m):
     return (7, 5) if m >= 300 else (3, 3)
 
 
-def collect_runs(start: int, count: int, out: str, lo: int, hi: int, threads: int):
+def collect_runs(start: int, count: int, out: str, lo: int, hi: int, threads: int, arms=None):
     """Per-run exploration: every training matrix is solved twice, once with the
     default rules (``policy = 1`` with no network: the defaults decide and every
     decision's features are logged) and once with one arm held for the whole
@@ -165,10 +168,11 @@ def collect_runs(start: int, count: int, out: str, lo: int, hi: int, threads: in
     binding.load_library()
     binding.policy_set(None)
     solver = Solver(hi)
-    rec = {"feat": [], "bins": [], "stats": [], "run": [], "t_def": [], "t_run": [], "arm": []}
+    arms = arms or ARMS
+    rec = {"feat": [], "bins": [], "stats": [], "run": [], "t_def": [], "t_run": [], "arm": [], "p_arm": []}
     t0 = time.time()
     for i, fam, H in producer(list(range(start, start + count)), "train", lo, hi, threads):
-        arm = ARMS[(i // 3) % len(ARMS)]
+        arm = arms[(i // 3) % len(arms)]
         binding.set_params(policy=1)
         t_def, info_d, _, _ = solver.solve(H, check=False)
         f0, b0, s0 = binding.policy_log()
@@ -184,6 +188,7 @@ def collect_runs(start: int, count: int, out: str, lo: int, hi: int, threads: in
             rec["t_def"].append(np.full(len(b), t_def, dtype=np.float32))
             rec["t_run"].append(np.full(len(b), t, dtype=np.float32))
             rec["arm"].append(np.full(len(b), kind, dtype=np.int32))
+            rec["p_arm"].append(np.full(len(b), 1.0 / len(arms), dtype=np.float32))
         log(f"[collect-run] {i} {fam} n={H.shape[0]} default {t_def:.2f}s arm {arm} {t_arm:.2f}s "
             f"info {info_d}/{info_a} elapsed {time.time() - t0:.0f}s")
         if (i - start + 1) % 10 == 0:
@@ -198,17 +203,20 @@ def _save_runs(out, rec):
     os.replace(tmp, out)
 
 
-def run_weights(t_def, t_run, arm, beta: float = 3.0, run=None):
+def run_weights(t_def, t_run, arm, beta: float = 3.0, run=None, p_arm=None):
     """Weights of the per-run data: an arm's solve counts
     exp(beta * log(t_default / t_arm)) times the number of arms (each arm is
     tried on 1/len(ARMS) of the matrices); a default solve counts 1.  With
     ``run`` (one id per solve's decisions; the default and the arm solve of a
     matrix have the same id but different ``arm``) a solve's weight is spread
     evenly over its decisions, so that a solve with more decisions does not
-    count more.  The network then prefers an arm over the defaults where the
-    arm was clearly faster on matrices with similar features."""
+    count more.  ``p_arm`` (per decision) is the probability with which the
+    solve's arm was drawn when exploration used fewer arms; the weight scales
+    with its inverse.  The network then prefers an arm over the defaults where
+    the arm was clearly faster on matrices with similar features."""
     adv = np.log(np.maximum(t_def, 1e-6) / np.maximum(t_run, 1e-6))
-    w = np.where(arm >= 0, len(ARMS) * np.exp(np.minimum(beta * adv, 8.0)), 1.0) / len(ARMS)
+    inv_p = len(ARMS) if p_arm is None else 1.0 / np.asarray(p_arm, dtype=np.float64)
+    w = np.where(arm >= 0, inv_p * np.exp(np.minimum(beta * adv, 8.0)), 1.0) / len(ARMS)
     if run is not None:
         key = np.asarray(run, dtype=np.int64) * 64 + (np.asarray(arm) + 1)
         _, inv, cnt = np.unique(key, return_inverse=True, return_counts=True)
@@ -238,9 +246,12 @@ def sample_weights(stats, run, beta: float = 1.5):
 
 
 def train(data_files, out: str, epochs: int = 30, batch: int = 4096, lr: float = 2e-3, seed: int = 0,
-          beta: float = 3.0):
+          beta: float = 3.0, first_only: bool = False):
     """Fit the network to per-decision data (``collect``) or per-run data
-    (``collect-run``, recognised by its per-solve times)."""
+    (``collect-run``, recognised by its per-solve times).  With ``first_only``
+    (per-run data) only the first decision of each solve is used, weighted by
+    its solve: the network then makes the per-matrix proposal of
+    ``policy = 4`` from the features of the whole matrix."""
     import torch
 
     from . import binding
@@ -252,8 +263,20 @@ def train(data_files, out: str, epochs: int = 30, batch: int = 4096, lr: float =
     stats = np.concatenate([p["stats"] for p in parts])
     run = np.concatenate([p["run"] for p in parts])
     if all("t_def" in p.files for p in parts):
-        w = run_weights(np.concatenate([p["t_def"] for p in parts]), np.concatenate([p["t_run"] for p in parts]),
-                        np.concatenate([p["arm"] for p in parts]), beta, run)
+        t_def = np.concatenate([p["t_def"] for p in parts])
+        t_run = np.concatenate([p["t_run"] for p in parts])
+        arm = np.concatenate([p["arm"] for p in parts])
+        p_arm = np.concatenate([p["p_arm"] if "p_arm" in p.files else np.full(len(p["arm"]), 1.0 / len(ARMS))
+                                for p in parts])
+        if first_only:
+            # decisions of one solve are stored together; keep the first of each
+            key = run.astype(np.int64) * 64 + (arm + 1)
+            _, first = np.unique(key, return_index=True)
+            sel = np.zeros(len(run), dtype=bool)
+            sel[first] = True
+            w = np.where(sel, run_weights(t_def, t_run, arm, beta, p_arm=p_arm), 0.0)
+        else:
+            w = run_weights(t_def, t_run, arm, beta, run, p_arm)
     else:
         w = sample_weights(stats, run)
     keep = w > 0
@@ -311,7 +334,7 @@ def summarize(rows):
 
 
 def evaluate(weights: str, start: int, count: int, lo: int, hi: int, min_conf: float, threads: int,
-             out: str | None = None):
+             out: str | None = None, policy: int = POLICY):
     """Held-out matrices solved with the default rules and with the network;
     with ``out`` the rows so far are saved every 10 matrices."""
     from . import binding
@@ -326,7 +349,7 @@ def evaluate(weights: str, start: int, count: int, lo: int, hi: int, min_conf: f
         binding.set_params(policy=0)
         t_def, info_d, be_d, oe_d = solver.solve(H)
         binding.policy_set(theta, min_conf)
-        binding.set_params(policy=1)
+        binding.set_params(policy=policy)
         t_net, info_n, be_n, oe_n = solver.solve(H)
         st = binding.get_stats()
         ok = info_n == 0 and be_n <= 50 * n * EPS and oe_n <= 50 * n * EPS
@@ -368,17 +391,20 @@ def main():
     cr.add_argument("--start", type=int, default=0)
     cr.add_argument("--count", type=int, default=100)
     cr.add_argument("--out", required=True)
+    cr.add_argument("--focused", action="store_true", help="explore only FOCUSED_ARMS")
     t = sub.add_parser("train")
     t.add_argument("data", nargs="+")
     t.add_argument("--out", default=SAVED)
     t.add_argument("--epochs", type=int, default=30)
     t.add_argument("--beta", type=float, default=3.0)
     t.add_argument("--batch", type=int, default=4096)
+    t.add_argument("--first-only", action="store_true")
     e = sub.add_parser("evaluate")
     e.add_argument("--weights", default=SAVED)
     e.add_argument("--start", type=int, default=0)
     e.add_argument("--count", type=int, default=200)
     e.add_argument("--min-conf", type=float, default=0.0)
+    e.add_argument("--policy", type=int, default=POLICY)
     e.add_argument("--out", default=None)
     for p in (c, cr, e):
         p.add_argument("--lo", type=int, default=1000)
@@ -388,12 +414,13 @@ def main():
     if args.cmd == "collect":
         collect(args.start, args.count, args.out, args.lo, args.hi, args.seed, args.threads)
     elif args.cmd == "collect-run":
-        collect_runs(args.start, args.count, args.out, args.lo, args.hi, args.threads)
+        collect_runs(args.start, args.count, args.out, args.lo, args.hi, args.threads,
+                     FOCUSED_ARMS if args.focused else None)
     elif args.cmd == "train":
-        train(args.data, args.out, args.epochs, batch=args.batch, beta=args.beta)
+        train(args.data, args.out, args.epochs, batch=args.batch, beta=args.beta, first_only=args.first_only)
     else:
         summary, rows = evaluate(args.weights, args.start, args.count, args.lo, args.hi, args.min_conf, args.threads,
-                                 args.out)
+                                 args.out, args.policy)
         print(json.dumps(summary), flush=True)
 
 
