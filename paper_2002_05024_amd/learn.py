@@ -1,22 +1,27 @@
 """Training and evaluation of the parameter-proposal network.
 
-Three stages, each run on a GPU:
+Stages, each run on a GPU:
 
-``collect``  solves matrices of three families (random N(0,1) Hessenberg,
-             prescribed-spectrum Hessenberg, row-graded Hessenberg) with
-             n uniform in [1000, 8000], with exploration switched on
-             (``policy = 2``: every iteration's shift-count and window bins drawn
-             at random), and stores each decision's features, bins, and the
-             deflations per millisecond that followed it.
-``train``    fits the network by reward-weighted cross-entropy with the
-             library's own GPU kernels (``neig_mlp_grad`` + ``neig_mlp_adam``):
-             a decision's weight grows with how much its reward beat the
-             typical reward of its own run, so the network imitates the better
-             choices.  Input normalisation (mu, sd) comes from the data.
-``evaluate`` solves held-out matrices with the default rules and with the
-             network (``policy = 1``), times both, and checks every result
-             (backward error and orthogonality <= 50 n eps); a result that fails
-             the check with the network is solved again with the default rules.
+``collect``      per-decision exploration (``policy = 2``: every iteration's
+                 shift-count and window bins drawn at random), storing each
+                 decision's features, bins and the deflations per millisecond
+                 that followed it.  (A first design; its rewards are myopic.)
+``collect-run``  per-run exploration: every training matrix (three families:
+                 random N(0,1), prescribed-spectrum and row-graded Hessenberg,
+                 n uniform in [1000, 8000]) is solved with the default rules and
+                 with one (shift, window) bin pair held for the whole solve
+                 (``policy = 3``); both solves' decisions and times are stored.
+``train``        fits the network by weighted cross-entropy with the library's
+                 own GPU kernels (``neig_mlp_grad`` + ``neig_mlp_adam``); for
+                 per-run data a solve weighs exp(beta log(t_default / t_solve))
+                 over its exploration probability, and ``--first-only`` keeps
+                 the first decision of each solve (a per-matrix proposal).
+                 Input normalisation (mu, sd) comes from the data.
+``evaluate``     solves held-out matrices with the default rules and with the
+                 network (``policy = 4`` by default: the first proposal holds for
+                 the whole solve), times both, and checks every result (backward
+                 error and orthogonality <= 50 n eps); a result that fails the
+                 check with the network is solved again with the default rules.
 
 Inputs are built on the host by worker threads in rounds between the timed
 solves (never during one).
