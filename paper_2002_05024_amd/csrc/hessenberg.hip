@@ -35,7 +35,8 @@
 #define HRD_THREADS 256
 #define HRD_RB 256       // rows per workgroup in k_hrd_a / k_hrd_b
 #define HRD_GR 512       // rows per workgroup in the GEMV (two per thread)
-#define HRD_GC 256       // vector entries per GEMV workgroup
+#define HRD_GC 256       // vector entries per GEMV workgroup (512 for large trailing blocks)
+#define HRD_GC_MAX 512
 
 struct HrdState {
     double alpha, beta, tau, scal;
@@ -52,6 +53,7 @@ struct HrdArgs {
     HrdState *st;
     int lda, ldw;
     int n, k0, m, i, jb, nch;  // nch: chunks of the previous GEMV
+    int cw;                    // vector entries per GEMV chunk (HRD_GC or HRD_GC_MAX)
 };
 
 // Sum x[c] (c < 64) over the 64 lanes of a wavefront by recursive halving:
@@ -352,13 +354,14 @@ extern "C" __global__ void __launch_bounds__(HRD_THREADS) k_hrd_b(HrdArgs p) {
 // z(r) = sum over the chunk's entries c of A(k0+1+r, k0+1+c) * scal * a(c),
 // a = column j's tail (local entries i+1..m-1).  Grid: row blocks x chunks.
 extern "C" __global__ void __launch_bounds__(HRD_THREADS) k_hrd_gemv(HrdArgs p) {
-    __shared__ double v[HRD_GC];
+    __shared__ double v[HRD_GC_MAX];
     const int t = threadIdx.x;
-    const int c0 = p.i + 1 + blockIdx.y * HRD_GC;
-    const int cn = min(HRD_GC, p.m - c0);
+    const int c0 = p.i + 1 + blockIdx.y * p.cw;
+    const int cn = min(p.cw, p.m - c0);
     const int j = p.k0 + p.i;
     const size_t base = (size_t)p.k0 + 1;
-    if (t < cn) v[t] = AT(p.A, p.lda, base + c0 + t, j) * p.st->scal;
+    const double scal = p.st->scal;
+    for (int u = t; u < cn; u += HRD_THREADS) v[u] = AT(p.A, p.lda, base + c0 + u, j) * scal;
     __syncthreads();
     const int r0 = blockIdx.x * HRD_GR + t, r1 = r0 + HRD_THREADS;
     const bool in0 = r0 < p.m, in1 = r1 < p.m;
@@ -366,22 +369,23 @@ extern "C" __global__ void __launch_bounds__(HRD_THREADS) k_hrd_gemv(HrdArgs p) 
     double a0 = 0.0, a1 = 0.0, b0 = 0.0, b1 = 0.0;
     int c = 0;
     if (in1) {
-        // eight independent loads in flight per lane before their first use
-        for (; c + 4 <= cn; c += 4) {
+        // sixteen independent loads in flight per lane before their first use
+        const size_t ld = (size_t)p.lda;
+        for (; c + 8 <= cn; c += 8) {
             const double *c1 = col + (size_t)c * p.lda;
-            const size_t ld = (size_t)p.lda;
-            const double x00 = c1[r0], x01 = c1[r1];
-            const double x10 = c1[ld + r0], x11 = c1[ld + r1];
-            const double x20 = c1[2 * ld + r0], x21 = c1[2 * ld + r1];
-            const double x30 = c1[3 * ld + r0], x31 = c1[3 * ld + r1];
-            a0 = fma(x00, v[c], a0);
-            a1 = fma(x01, v[c], a1);
-            b0 = fma(x10, v[c + 1], b0);
-            b1 = fma(x11, v[c + 1], b1);
-            a0 = fma(x20, v[c + 2], a0);
-            a1 = fma(x21, v[c + 2], a1);
-            b0 = fma(x30, v[c + 3], b0);
-            b1 = fma(x31, v[c + 3], b1);
+            double x0[8], x1[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                x0[u] = c1[u * ld + r0];
+                x1[u] = c1[u * ld + r1];
+            }
+#pragma unroll
+            for (int u = 0; u < 8; u += 2) {
+                a0 = fma(x0[u], v[c + u], a0);
+                a1 = fma(x1[u], v[c + u], a1);
+                b0 = fma(x0[u + 1], v[c + u + 1], b0);
+                b1 = fma(x1[u + 1], v[c + u + 1], b1);
+            }
         }
         for (; c < cn; ++c) {
             const double *c1 = col + (size_t)c * p.lda;

@@ -966,7 +966,7 @@ void hessenberg_run(int n, double *A, int lda, double *Q, int ldq, hipStream_t s
     double *V = ws.hrd, *Y = V + (size_t)ldw * NB, *P = Y + (size_t)ldw * NB, *Mt = P + (size_t)ldw * NB;
     double *T = Mt + (size_t)ldw * NB, *Gt = T + (size_t)NB * NB;
     double *part = Gt + (size_t)NB * NB, *zpart = part + nrb_max * (NB + 2), *sk = zpart + nch_max * ldw;
-    HrdArgs ha{A, V, Y, T, part, zpart, ws.hrd_st, lda, ldw, n, 0, 0, 0, 0, 0};
+    HrdArgs ha{A, V, Y, T, part, zpart, ws.hrd_st, lda, ldw, n, 0, 0, 0, 0, 0, HRD_GC};
     for (int k0 = 0; k0 < n - 2; k0 += NB) {
         const int jb = std::min(NB, n - 2 - k0);
         const int m = n - k0 - 1;
@@ -974,6 +974,9 @@ void hessenberg_run(int n, double *A, int lda, double *Q, int ldq, hipStream_t s
         ha.k0 = k0;
         ha.m = m;
         ha.jb = jb;
+        // wider GEMV chunks on large trailing blocks: fewer partial sums per row
+        // while the grid still has thousands of workgroups
+        ha.cw = m > 8192 ? HRD_GC_MAX : HRD_GC;
         int nch = 0;
         for (int i = 0; i <= jb; ++i) {
             ha.i = i;
@@ -981,7 +984,7 @@ void hessenberg_run(int n, double *A, int lda, double *Q, int ldq, hipStream_t s
             if (i > 0) hipLaunchKernelGGL(k_hrd_a, dim3(nrb), dim3(HRD_THREADS), 0, s, ha);
             if (i == jb) break;
             hipLaunchKernelGGL(k_hrd_b, dim3(nrb), dim3(HRD_THREADS), 0, s, ha);
-            nch = (m - i - 1 + HRD_GC - 1) / HRD_GC;
+            nch = (m - i - 1 + ha.cw - 1) / ha.cw;
             hipLaunchKernelGGL(k_hrd_gemv, dim3((m + HRD_GR - 1) / HRD_GR, nch), dim3(HRD_THREADS), 0, s, ha);
         }
         const int nt = n - k0 - jb;  // trailing columns k0 + jb .. n-1

@@ -138,3 +138,22 @@ def test_pipeline_prescribed_n4000(neig):
     assert structure_violations(S, r.wr.cpu().numpy(), r.wi.cpu().numpy()) == []
     got = np.sort_complex(r.wr.cpu().numpy() + 1j * r.wi.cpu().numpy())
     assert np.abs(got - np.sort_complex(lam)).max() <= 1e-9
+
+
+def test_hessenberg_padded_leading_dimensions(neig):
+    """lda, ldq > n: the padding rows are neither read into the result nor written."""
+    import torch
+
+    n, pad = 150, 7
+    A = inputs.rng(91, n).standard_normal((n, n))
+    H1, Q1 = gpu_reduce(neig, A)
+    Ab = torch.full((n, n + pad), 7.5, dtype=torch.float64, device="cuda")
+    Qb = torch.full((n, n + pad), -3.25, dtype=torch.float64, device="cuda")
+    Ad = Ab.t()[:n, :]  # column-major n x n view, leading dimension n + pad
+    Qd = Qb.t()[:n, :]
+    Ad.copy_(torch.from_numpy(A).cuda())
+    Qd.copy_(torch.eye(n, dtype=torch.float64, device="cuda"))
+    assert Ad.stride() == (1, n + pad)
+    neig.hessenberg(Ad, Qd)
+    assert np.array_equal(to_host(Ad), H1) and np.array_equal(to_host(Qd), Q1)
+    assert bool((Ab.t()[n:, :] == 7.5).all()) and bool((Qb.t()[n:, :] == -3.25).all())
