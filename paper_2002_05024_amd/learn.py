@@ -229,6 +229,45 @@ def run_weights(t_def, t_run, arm, beta: float = 3.0, run=None, p_arm=None):
     return w
 
 
+def per_matrix_rows(run, arm, t_def, t_run, feat):
+    """One row per training matrix of per-run data: the features of its default
+    solve's first decision, the arm its other solve held, and that solve's
+    advantage log(t_default / t_arm).  Returns (ids, X, arms, adv)."""
+    key = run.astype(np.int64) * 64 + (arm + 1)
+    _, first = np.unique(key, return_index=True)
+    mats = {}
+    for i in first:
+        d = mats.setdefault(int(run[i]), {})
+        if arm[i] < 0:
+            d["x"] = feat[i]
+        else:
+            d["arm"] = int(arm[i])
+            d["adv"] = float(np.log(max(t_def[i], 1e-6) / max(t_run[i], 1e-6)))
+    ids = np.array(sorted(r for r, d in mats.items() if "x" in d and "arm" in d), dtype=np.int64)
+    X = np.array([mats[r]["x"] for r in ids], dtype=np.float64).reshape(len(ids), -1)
+    return ids, X, np.array([mats[r]["arm"] for r in ids]), np.array([mats[r]["adv"] for r in ids])
+
+
+def smoothed_targets(X, arms, adv, k: int = 25, beta: float = 8.0):
+    """Per-matrix soft targets over (default, arms): for each matrix, the mean
+    advantage of every arm among its k nearest matrices in normalised feature
+    space (each matrix tried one arm), then softmax(beta * advantage) with the
+    default rules at advantage 0.  Returns a list, per matrix, of
+    ((shift bin, window bin), probability)."""
+    Z = (X - X.mean(axis=0)) / (X.std(axis=0) + 1e-3)
+    out = []
+    for i in range(len(X)):
+        nb = np.argsort(np.linalg.norm(Z - Z[i], axis=1), kind="stable")[:k]
+        by = {}
+        for j in nb:
+            by.setdefault(int(arms[j]), []).append(adv[j])
+        choices = [((7, 5), 0.0)] + [(ARMS[a], float(np.mean(v))) for a, v in sorted(by.items())]
+        w = np.exp(beta * np.array([v for _, v in choices]))
+        w /= w.sum()
+        out.append([(b, float(p)) for (b, _), p in zip(choices, w)])
+    return out
+
+
 def _save(out, feats, bins, stats, runs):
     tmp = out + ".tmp.npz"
     np.savez_compressed(tmp, feat=np.concatenate(feats), bins=np.concatenate(bins), stats=np.concatenate(stats),
@@ -251,7 +290,7 @@ def sample_weights(stats, run, beta: float = 1.5):
 
 
 def train(data_files, out: str, epochs: int = 30, batch: int = 4096, lr: float = 2e-3, seed: int = 0,
-          beta: float = 3.0, first_only: bool = False):
+          beta: float = 3.0, first_only: bool = False, smooth_k: int = 0):
     """Fit the network to per-decision data (``collect``) or per-run data
     (``collect-run``, recognised by its per-solve times).  With ``first_only``
     (per-run data) only the first decision of each solve is used, weighted by
@@ -267,7 +306,17 @@ def train(data_files, out: str, epochs: int = 30, batch: int = 4096, lr: float =
     bins = np.concatenate([p["bins"] for p in parts])
     stats = np.concatenate([p["stats"] for p in parts])
     run = np.concatenate([p["run"] for p in parts])
-    if all("t_def" in p.files for p in parts):
+    if smooth_k > 0:
+        # per-matrix soft targets from the k nearest training matrices
+        ids, Xm, arms, adv = per_matrix_rows(run, np.concatenate([p["arm"] for p in parts]),
+                                             np.concatenate([p["t_def"] for p in parts]),
+                                             np.concatenate([p["t_run"] for p in parts]), feat)
+        rows = [(x, b, pr) for x, tg in zip(Xm, smoothed_targets(Xm, arms, adv, smooth_k, beta)) for b, pr in tg]
+        feat = np.array([x for x, _, _ in rows])
+        bins = np.array([b for _, b, _ in rows], dtype=np.int32)
+        w = np.array([pr for _, _, pr in rows])
+        run = np.zeros(len(w), dtype=np.int32)
+    elif all("t_def" in p.files for p in parts):
         t_def = np.concatenate([p["t_def"] for p in parts])
         t_run = np.concatenate([p["t_run"] for p in parts])
         arm = np.concatenate([p["arm"] for p in parts])
@@ -404,6 +453,8 @@ def main():
     t.add_argument("--beta", type=float, default=3.0)
     t.add_argument("--batch", type=int, default=4096)
     t.add_argument("--first-only", action="store_true")
+    t.add_argument("--smooth-k", type=int, default=0,
+                   help="per-matrix targets smoothed over the k nearest training matrices")
     e = sub.add_parser("evaluate")
     e.add_argument("--weights", default=SAVED)
     e.add_argument("--start", type=int, default=0)
@@ -422,7 +473,8 @@ def main():
         collect_runs(args.start, args.count, args.out, args.lo, args.hi, args.threads,
                      FOCUSED_ARMS if args.focused else None)
     elif args.cmd == "train":
-        train(args.data, args.out, args.epochs, batch=args.batch, beta=args.beta, first_only=args.first_only)
+        train(args.data, args.out, args.epochs, batch=args.batch, beta=args.beta, first_only=args.first_only,
+              smooth_k=args.smooth_k)
     else:
         summary, rows = evaluate(args.weights, args.start, args.count, args.lo, args.hi, args.min_conf, args.threads,
                                  args.out, args.policy)

@@ -107,3 +107,28 @@ def test_run_weights_spread_over_decisions():
     assert w[0] == pytest.approx(scale / k)
     assert np.allclose(w[1:4], 2.0 / 3 * scale)  # a solve's weight split over its decisions
     assert np.allclose(w[4:6], 0.5 / k * scale) and np.allclose(w[6:8], 0.5 * scale)
+
+
+def test_smoothed_targets_follow_the_neighbourhood():
+    from paper_2002_05024_amd import learn
+
+    g = np.random.default_rng(0)
+    # two well separated groups of matrices; arm (7, 3) is faster in group A,
+    # slower in group B; the other arm tried is neutral
+    XA = g.normal(0.0, 0.1, (20, 24))
+    XB = g.normal(5.0, 0.1, (20, 24))
+    X = np.vstack([XA, XB])
+    a73, a55 = learn.ARMS.index((7, 3)), learn.ARMS.index((5, 5))
+    arms = np.array([a73, a55] * 20)
+    adv = np.where(np.arange(40) < 20, np.where(arms == a73, 0.3, 0.0), np.where(arms == a73, -0.5, 0.0))
+    T = learn.smoothed_targets(X, arms, adv, k=10, beta=8.0)
+    for i in range(40):
+        probs = dict(T[i])
+        assert abs(sum(probs.values()) - 1.0) < 1e-12
+        best = max(probs, key=probs.get)
+        assert best == ((7, 3) if i < 20 else (7, 5)) or (i >= 20 and best == (5, 5))
+    ids, Xm, am, av = learn.per_matrix_rows(np.array([0, 0, 0, 1, 1]), np.array([-1, -1, 4, -1, 2]),
+                                            np.array([2.0] * 5), np.array([2.0, 2.0, 1.0, 2.0, 4.0]),
+                                            np.arange(5, dtype=float)[:, None] * np.ones((1, 3)))
+    assert list(ids) == [0, 1] and list(am) == [4, 2]
+    assert np.allclose(av, [np.log(2.0), np.log(0.5)]) and np.allclose(Xm[:, 0], [0.0, 3.0])
