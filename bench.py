@@ -54,6 +54,8 @@ def parse():
     ap.add_argument("--reorder", type=int, default=1, help="also time the eigenvalue reordering at n=4000")
     ap.add_argument("--hessenberg", type=int, default=20000,
                     help="order of the dense matrix for the Hessenberg-reduction leg (0 skips it)")
+    ap.add_argument("--learned", type=int, default=9,
+                    help="held-out matrices (n in [1000, 3000]) for the proposal-network leg (0 skips it)")
     return ap.parse_args()
 
 
@@ -267,6 +269,25 @@ def hessenberg_leg(args, dev):
     return out
 
 
+def learned_leg(args, dev):
+    """The proposal network against the default rules on the first held-out
+    matrices of the learned workload (three families, n in [1000, 3000] to keep
+    the leg short), each solved both ways; GPU time by HIP events, every result
+    checked (backward error and orthogonality <= 50 n eps)."""
+    import os
+
+    from paper_2002_05024_amd import learn
+
+    if not os.path.exists(learn.SAVED):
+        return {"skipped": "no trained network"}
+    summary, rows = learn.evaluate(learn.SAVED, 0, args.learned, 1000, 3000, 0.0, 8)
+    return {"workload": f"{len(rows)} held-out matrices (random / prescribed / graded), n in [1000, 3000]",
+            "default_s": round(summary["total_default_s"], 3), "network_s": round(summary["total_net_s"], 3),
+            "speedup": round(summary["speedup"], 3), "all_within_50n_eps": summary["all_ok"],
+            "per_family": {f: {k: round(v, 3) for k, v in d.items()} for f, d in summary["per_family"].items()},
+            "policy": learn.POLICY}
+
+
 def batched_leg(args, dev):
     """The batched workload: ``batch_count`` problems with n uniform in [32, 1024],
     half random N(0,1) Hessenberg and half prescribed-spectrum Hessenberg, Z from
@@ -379,6 +400,8 @@ def main():
             line["reorder"] = reorder_leg(args, dev)
         if args.hessenberg:
             line["hessenberg"] = hessenberg_leg(args, dev)
+        if args.learned:
+            line["learned"] = learned_leg(args, dev)
         print(json.dumps(line), flush=True)
         return
     n = args.n
@@ -457,7 +480,7 @@ def main():
     if args.check:
         be, oe = backward_and_orth(H0, H, Z)
         line["check"] = {"backward_error": be, "orthogonality": oe, "bound_50n_eps": 50 * n * 2.0 ** -52}
-    if args.batched or args.reorder or args.hessenberg:
+    if args.batched or args.reorder or args.hessenberg or args.learned:
         del H, Z, H0
         torch.cuda.empty_cache()
     if args.batched:
@@ -466,6 +489,8 @@ def main():
         line["reorder"] = reorder_leg(args, dev)
     if args.hessenberg:
         line["hessenberg"] = hessenberg_leg(args, dev)
+    if args.learned:
+        line["learned"] = learned_leg(args, dev)
     if args.cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(args.cpu_n, n)
     print(json.dumps(line), flush=True)
