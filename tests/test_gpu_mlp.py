@@ -189,3 +189,40 @@ def test_network_proposals_are_valid(neig):
     finally:
         neig.set_params(policy=0)
         neig.policy_set(None)
+
+
+def test_fixed_bins_per_run_are_applied_and_logged(neig):
+    """policy = 3 holds the bin pair encoded in the seed at every decision."""
+    H = inputs.random_hessenberg(600, inputs.rng(inputs.LEARNED, 3))
+    neig.set_params(policy=3, seed=3 + 8 * 6)  # 16 shifts, 80-row window
+    try:
+        _solve_and_check(neig, H, "per-run")
+        feat, bins, st = neig.policy_log()
+        stats = neig.get_stats()
+    finally:
+        neig.set_params(policy=0, seed=0)
+    assert len(bins) > 0 and np.all(bins[:, 0] == 3) and np.all(bins[:, 1] == 6)
+    # a decision is logged when an AED follows it
+    assert stats["policy_used"] >= len(bins) and stats["policy_fallback"] == 0
+
+
+def test_per_matrix_proposal_holds_the_first_decision(neig):
+    """policy = 4: the network is consulted once, its bins hold for the whole
+    solve (one logged decision, every later decision counted as used); without
+    a network the default rules decide everywhere."""
+    theta = mlp.init(11)
+    H = inputs.random_hessenberg(600, inputs.rng(inputs.LEARNED, 4))
+    neig.policy_set(theta.astype(np.float32), 0.0)
+    neig.set_params(policy=4)
+    try:
+        _solve_and_check(neig, H, "per-matrix")
+        feat, bins, st = neig.policy_log()
+        stats = neig.get_stats()
+        assert len(bins) <= 1 and stats["policy_used"] >= 1 and stats["policy_fallback"] == 0
+        neig.policy_set(None)
+        _solve_and_check(neig, H, "per-matrix, no network")
+        stats = neig.get_stats()
+        assert stats["policy_used"] == 0 and stats["policy_fallback"] >= 1
+    finally:
+        neig.set_params(policy=0)
+        neig.policy_set(None)
