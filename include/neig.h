@@ -12,7 +12,11 @@
  * window by window, with each window's reflectors accumulated into a small
  * orthogonal matrix that is applied to the off-diagonal parts of H and Z with
  * matrix-matrix products (Section 3.2, the window / left-update / right-update
- * tasks).
+ * tasks).  Around it: many independent problems in one launch
+ * (neig_schur_batched), the Hessenberg reduction that precedes it
+ * (neig_hessenberg, Section 3.1), eigenvalue reordering of the result
+ * (neig_reorder), and a small network that proposes the shift count and AED
+ * window (neig_policy_*, neig_mlp_*).
  *
  * Conventions for every entry point:
  *   - matrices are FP64, column-major, element (i, j) at p[i + j*ld], ld >= max(1, n);

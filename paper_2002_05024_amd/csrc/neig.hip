@@ -966,6 +966,10 @@ void hessenberg_run(int n, double *A, int lda, double *Q, int ldq, hipStream_t s
     double *V = ws.hrd, *Y = V + (size_t)ldw * NB, *P = Y + (size_t)ldw * NB, *Mt = P + (size_t)ldw * NB;
     double *T = Mt + (size_t)ldw * NB, *Gt = T + (size_t)NB * NB;
     double *part = Gt + (size_t)NB * NB, *zpart = part + nrb_max * (NB + 2), *sk = zpart + nch_max * ldw;
+    // the two workgroup counters start at zero (the last workgroup of every
+    // column kernel resets its counter; this also clears them after an
+    // interrupted call)
+    ck(hipMemsetAsync(ws.hrd_st, 0, sizeof(HrdState), s));
     HrdArgs ha{A, V, Y, T, part, zpart, ws.hrd_st, lda, ldw, n, 0, 0, 0, 0, 0, HRD_GC};
     for (int k0 = 0; k0 < n - 2; k0 += NB) {
         const int jb = std::min(NB, n - 2 - k0);
