@@ -382,7 +382,7 @@ def batched_leg(args, dev):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}), flush=True)
+        print(json.dumps({"error": "one GPU only: the library runs on a single GPU (multi-GPU sharding is designed, not implemented); --gpus must be 1"}), flush=True)
         sys.exit(2)
     import torch
 
