@@ -801,9 +801,11 @@ class Solver {
     // selected as a whole) to the leading diagonal block, keeping their order.
     // Windows of at most REORDER_WMAX rows: in each, the selected blocks go to
     // the window's top (k_reorder_window) and the window's factor is applied to
-    // the rest of S and to Z by the update kernel.  The next window starts at
-    // the first selected block not yet in place, reaching at most REORDER_WMAX
-    // rows up, so each window moves that block up by most of a window.
+    // the rest of S and to Z by the update kernel.  Each window ends at the last
+    // block of a group of selected blocks (the first one not yet in place and
+    // those following it within a window, at most a third of a window of
+    // rows) and reaches at most REORDER_WMAX rows up, so each window moves the
+    // whole group up by most of a window.
     // Returns 0, or 1 when a swap was rejected (S, Z remain a valid Schur
     // decomposition, partly reordered).  *m = selected eigenvalues in place.
     int reorder(std::vector<int> sel, int *m_out) {
@@ -834,9 +836,23 @@ class Solver {
                 placed += bs;
                 continue;
             }
-            int lo = std::max(placed, p + bs - W);
+            // a group: the selected blocks from p on whose ends lie within W rows
+            // of p, at most W/3 selected rows, so that one window moves them all
+            // up by at least 2W/3 rows (fewer windows, updates and read-backs
+            // than one block at a time; the swaps are the same)
+            int gend = p + bs, grows = bs;
+            for (int j = gend; j < n && grows < W / 3;) {
+                const int bj = bsize(j);
+                if (j + bj - p > W) break;
+                if (sel[j]) {
+                    gend = j + bj;
+                    grows += bj;
+                }
+                j += bj;
+            }
+            int hi = gend;
+            int lo = std::max(placed, hi - W);
             if (lo > placed && nz[lo]) ++lo;      // do not split the 2x2 block at lo-1, lo
-            int hi = std::min(n, lo + W);
             if (hi < n && nz[hi]) --hi;           // nor the one at hi-1, hi
             const int w = hi - lo;
             ReorderFlags f;
