@@ -125,6 +125,11 @@ struct DeviceWs {
     // Hessenberg reduction: V, Y, T, partials (one block, carved per call) and
     // the column state with its two workgroup counters (zero between launches)
     double *hrd = nullptr; size_t hrd_cap = 0;
+    // reordering: window descriptors and statuses of one round
+    ReorderWin *rwin = nullptr; size_t rwin_cap = 0;
+    ReorderWin *h_rwin = nullptr; size_t h_rwin_cap = 0;
+    int *rstat = nullptr; size_t rstat_cap = 0;
+    int *h_rstat = nullptr; size_t h_rstat_cap = 0;
     HrdState *hrd_st = nullptr;
 };
 
@@ -172,9 +177,11 @@ void free_workspace(DeviceWs &w) {
     if (!w.ready) return;
     for (void *p : {(void *)w.ut, (void *)w.vt, (void *)w.poly, (void *)w.dbuf, (void *)w.rot, (void *)w.ist,
                     (void *)w.flag, (void *)w.bprob, (void *)w.border, (void *)w.bnext,
-                    (void *)w.theta, (void *)w.pol_out, (void *)w.mlp_part, (void *)w.hrd, (void *)w.hrd_st})
+                    (void *)w.theta, (void *)w.pol_out, (void *)w.mlp_part, (void *)w.hrd, (void *)w.hrd_st,
+                    (void *)w.rwin, (void *)w.rstat})
         if (p) (void)hipFree(p);
-    for (void *p : {(void *)w.h_ist, (void *)w.h_dbuf, (void *)w.h_poly, (void *)w.h_flag, (void *)w.h_pol_out})
+    for (void *p : {(void *)w.h_ist, (void *)w.h_dbuf, (void *)w.h_poly, (void *)w.h_flag, (void *)w.h_pol_out,
+                    (void *)w.h_rwin, (void *)w.h_rstat})
         if (p) (void)hipHostFree(p);
     for (hipEvent_t e : w.events) (void)hipEventDestroy(e);
     w = DeviceWs();
@@ -826,60 +833,92 @@ class Solver {
         int total = 0;
         for (int j = 0; j < n; ++j) total += sel[j];
         grow(&ws_.vt, &ws_.vt_cap, (size_t)W * W);
+        // per-round window descriptors (device, with a pinned host mirror),
+        // factors and statuses for up to kMaxWins concurrent windows
+        const int kMaxWins = std::max(1, std::min(ws_.cus, 64));
+        grow(&ws_.vt, &ws_.vt_cap, (size_t)kMaxWins * W * W);
+        grow(&ws_.rwin, &ws_.rwin_cap, (size_t)kMaxWins);
+        grow_host(&ws_.h_rwin, &ws_.h_rwin_cap, (size_t)kMaxWins);
+        grow(&ws_.rstat, &ws_.rstat_cap, (size_t)2 * kMaxWins);
+        grow_host(&ws_.h_rstat, &ws_.h_rstat_cap, (size_t)2 * kMaxWins);
         int placed = 0, info = 0;
         while (placed < total) {
-            int p = placed;
-            while (p < n && !sel[p]) p += bsize(p);
-            if (p >= n) break;
-            const int bs = bsize(p);
-            if (p == placed) {
-                placed += bs;
+            // one round: windows for successive groups of selected blocks, each
+            // window ending at its group's last block and starting at most W rows
+            // up but not above the previous window's end (windows never overlap)
+            const int placed_before = placed;
+            int nwin = 0, floor_row = placed, p = placed;
+            while (nwin < kMaxWins) {
+                while (p < n && !sel[p]) p += bsize(p);
+                if (p >= n) break;
+                const int bs = bsize(p);
+                if (p == floor_row) {  // already in place behind the previous group
+                    if (nwin == 0) placed += bs;
+                    floor_row = p + bs;
+                    p += bs;
+                    continue;
+                }
+                int gend = p + bs, grows = bs, j = gend;
+                while (j < n && grows < W / 3) {
+                    const int bj = bsize(j);
+                    if (j + bj - p > W) break;
+                    if (sel[j]) {
+                        gend = j + bj;
+                        grows += bj;
+                    }
+                    j += bj;
+                }
+                int hi = gend;
+                int lo = std::max(floor_row, hi - W);
+                if (lo > floor_row && nz[lo]) ++lo;  // do not split the 2x2 block at lo-1, lo
+                if (hi < n && nz[hi]) --hi;           // nor the one at hi-1, hi
+                ReorderWin &rw = ws_.h_rwin[nwin++];
+                rw.off = lo;
+                rw.w = hi - lo;
+                for (int t = 0; t < rw.w; ++t) rw.sel[t] = sel[lo + t];
+                floor_row = hi;
+                p = hi;
+            }
+            if (nwin == 0) {  // only blocks already in place were passed
+                if (placed == placed_before) break;
                 continue;
             }
-            // a group: the selected blocks from p on whose ends lie within W rows
-            // of p, at most W/3 selected rows, so that one window moves them all
-            // up by at least 2W/3 rows (fewer windows, updates and read-backs
-            // than one block at a time; the swaps are the same)
-            int gend = p + bs, grows = bs;
-            for (int j = gend; j < n && grows < W / 3;) {
-                const int bj = bsize(j);
-                if (j + bj - p > W) break;
-                if (sel[j]) {
-                    gend = j + bj;
-                    grows += bj;
-                }
-                j += bj;
-            }
-            int hi = gend;
-            int lo = std::max(placed, hi - W);
-            if (lo > placed && nz[lo]) ++lo;      // do not split the 2x2 block at lo-1, lo
-            if (hi < n && nz[hi]) --hi;           // nor the one at hi-1, hi
-            const int w = hi - lo;
-            ReorderFlags f;
-            std::memset(&f, 0, sizeof(f));
-            for (int t = 0; t < w; ++t) f.sel[t] = sel[lo + t];
-            const size_t lds = (size_t)(2 * w * (w + 1)) * sizeof(double);
+            ck(hipMemcpyAsync(ws_.rwin, ws_.h_rwin, (size_t)nwin * sizeof(ReorderWin), hipMemcpyHostToDevice, st_));
+            const size_t lds = (size_t)(2 * W * (W + 1)) * sizeof(double);
             timed(kSmall, [&] {
-                hipLaunchKernelGGL(k_reorder_window, dim3(1), dim3(NT), lds, st_, H_, ldh_, lo, w, f, ws_.vt, w,
-                                   ws_.ist);
+                hipLaunchKernelGGL(k_reorder_window, dim3(nwin), dim3(NT), lds, st_, H_, ldh_, ws_.rwin, ws_.vt, W,
+                                   ws_.rstat);
                 ck(hipGetLastError());
             });
-            std::vector<Task> tasks;
-            add_block_updates(tasks, lo, hi - 1, ws_.vt, w);
-            run_updates(tasks);
-            ck(hipMemcpyAsync(ws_.h_ist, ws_.ist, 2 * sizeof(int), hipMemcpyDeviceToHost, st_));
-            std::vector<double> g = gather(lo, hi - 1);  // also waits for the status copy
-            const int k = ws_.h_ist[0];
-            for (int t = 0; t < w; ++t) {
-                sel[lo + t] = t < k ? 1 : 0;
-                if (t > 0) nz[lo + t] = g[w + t] != 0.0;
+            // left updates (rows of a window, columns right of it) touch rows the
+            // right updates of later windows also touch in other columns: two launches
+            std::vector<Task> left, right;
+            for (int b = 0; b < nwin; ++b) {
+                const ReorderWin &rw = ws_.h_rwin[b];
+                const double *ut = ws_.vt + (size_t)b * W * W;
+                const int lo = rw.off, hi = rw.off + rw.w - 1;
+                if (hi + 1 < n) left.push_back({H_ + lo + (size_t)(hi + 1) * ldh_, ut, ldh_, W, rw.w, n - hi - 1, 0});
+                if (lo > 0) right.push_back({H_ + (size_t)lo * ldh_, ut, ldh_, W, rw.w, lo, 1});
+                right.push_back({Z_ + (size_t)lo * ldz_, ut, ldz_, W, rw.w, n, 1});
             }
-            stats_.small_solves++;
-            if (ws_.h_ist[1]) {
-                info = 1;
-                break;
+            run_updates(left);
+            run_updates(right);
+            ck(hipMemcpyAsync(ws_.h_rstat, ws_.rstat, (size_t)2 * nwin * sizeof(int), hipMemcpyDeviceToHost, st_));
+            const int glo = ws_.h_rwin[0].off, ghi = ws_.h_rwin[nwin - 1].off + ws_.h_rwin[nwin - 1].w - 1;
+            std::vector<double> g = gather(glo, ghi);  // also waits for the status copy
+            const int gm = ghi - glo + 1;
+            for (int b = 0; b < nwin; ++b) {
+                const ReorderWin &rw = ws_.h_rwin[b];
+                const int k = ws_.h_rstat[2 * b];
+                for (int t = 0; t < rw.w; ++t) {
+                    sel[rw.off + t] = t < k ? 1 : 0;
+                    if (t > 0) nz[rw.off + t] = g[gm + (rw.off + t - glo)] != 0.0;
+                }
+                if (ws_.h_rstat[2 * b + 1]) info = 1;
+                stats_.small_solves++;
             }
-            if (lo == placed) placed += k;
+            if (info) break;
+            if (ws_.h_rwin[0].off == placed) placed += ws_.h_rstat[0];
         }
         *m_out = placed;
         return info;

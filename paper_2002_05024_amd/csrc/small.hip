@@ -987,11 +987,14 @@ k_aed(double *H, int ldh, int ktop, int kbot, int nw, double hnorm, double smlnu
 
 #define REORDER_WMAX 96
 
-struct ReorderFlags {
+struct ReorderWin {
+    int off, w;             // the window: rows/cols off .. off+w-1 of S
     int sel[REORDER_WMAX];  // 1 at the positions of selected eigenvalues of the window
 };
 
-// Reorder a w x w diagonal window of the quasi-triangular S at (off, off): the
+// Reorder non-overlapping w x w diagonal windows of the quasi-triangular S, one
+// workgroup per window (window b = wins[blockIdx.x]; its factor goes to
+// Vt + b * ldvt * ldvt, its status to status + 2 b).  In each window at (off, off): the
 // selected blocks move to the top of the window in their order, by swaps of
 // adjacent diagonal blocks (the block exchange the paper's reordering phase
 // uses), with the window's orthogonal factor accumulated in LDS.  The window
@@ -1001,8 +1004,12 @@ struct ReorderFlags {
 // was rejected (the window is then partly reordered, still a valid Schur form).
 // The caller applies Vt to the rest of S and to Z.
 extern "C" __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(1, 1)))
-k_reorder_window(double *S, int lds_, int off, int w, ReorderFlags f, double *Vt, int ldvt, int *status) {
+k_reorder_window(double *S, int lds_, const ReorderWin *wins, double *Vt_all, int ldvt, int *status_all) {
     extern __shared__ double lds[];
+    const ReorderWin &f = wins[blockIdx.x];
+    const int off = f.off, w = f.w;
+    double *Vt = Vt_all + (size_t)blockIdx.x * ldvt * ldvt;
+    int *status = status_all + 2 * blockIdx.x;
     const int ld = w + 1;
     double *T = lds, *V = lds + (size_t)w * ld;
     lds_load_block(S, lds_, off, w, T, ld, V, ld);
