@@ -230,8 +230,9 @@ int neig_hessenberg(int n, double *A, int lda, double *Q, int ldq, hipStream_t s
  * the selected eigenvalues occupy the leading diagonal block of Q^T S Q, in
  * their original order, by exchanges of adjacent diagonal blocks (the
  * Sylvester-equation construction of Bai and Demmel), organised in windows of
- * at most 96 rows whose factors are applied to the rest of S and to Z with
- * FP64 matrix-core products.
+ * at most 96 rows, each moving a group of selected blocks; the windows of one
+ * round do not overlap and run concurrently, and their factors are applied to
+ * the rest of S and to Z with FP64 matrix-core products.
  *   S, lds   device; on entry a standardised real Schur form (as neig_schur
  *            returns it); on exit the reordered one.
  *   Z, ldz   device; on exit Z_in * Q.
