@@ -8,6 +8,12 @@
 // undeflated Ritz values as shifts.  Each AED and each small solve ends with one
 // small device-to-host read of its status; sweeps are launched without
 // synchronisation.  All launches go to the caller's stream.
+//
+// Also here: the batched entry points (descriptor packing and the persistent
+// solver of batched.hip), eigenvalue reordering (rounds of concurrent windows,
+// k_reorder_window in small.hip), the Hessenberg reduction (hessenberg.hip),
+// the proposal network's hooks and kernels (mlp.hip), and the per-device
+// workspace.
 #include "neig.h"
 
 #include "small.hip"
