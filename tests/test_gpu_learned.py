@@ -2,7 +2,10 @@
 held-out matrices of the three training families (random N(0,1), prescribed
 spectrum, row-graded Hessenberg), with the backward-error check judging every
 result.  The network's weights are the committed file written by the
-training stage of ``paper_2002_05024_amd.learn``."""
+training stage of ``paper_2002_05024_amd.learn``; it is used as that module's
+evaluation uses it (one proposal per matrix, ``policy = 4``).  The gain is
+printed per matrix and in total; the full held-out evaluation (200 matrices)
+is run by ``learn evaluate``."""
 import os
 
 import numpy as np
