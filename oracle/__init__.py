@@ -4,7 +4,9 @@ Plain, slow, single-threaded FP64 reference written from the textbook
 definitions the paper relies on (Section 2, eq. 3 and eq. 4; Section 3.2 for the
 double-shift bulge chase).  Only the tests, ``__graft_entry__.smoke()`` and the
 CPU-baseline leg of ``bench.py`` may import this package.  It shares no code with
-the GPU library and never calls it.
+the GPU library and never calls it; the two sides implement the same readings
+of the paper (deflation criteria, exceptional shift, reflector sign
+convention), each in code of its own.
 
 The numerical work lives in ``neig_oracle.c`` (compiled with gcc into
 ``liboracle.so`` next to this file by :func:`build`); this module only marshals

@@ -87,69 +87,66 @@ __device__ __forceinline__ Refl make_refl(double x0, double x1, double x2) {
     return r;
 }
 
-// Standardisation of one 2x2 block B = [[a b][c d]] (real Schur form, eq. 4):
-// G = [[cs -sn][sn cs]] with G^T B G upper triangular (real eigenvalues) or with
-// equal diagonal entries and b' c' < 0 (complex pair).  Reasoning: with
-// p = (a - d)/2 a rotation by t turns (p, (b + c)/2) by 2t and keeps (b - c)/2 and
-// the trace; p^2 + bc decides real versus complex.
+// Standardisation of one 2x2 block of a real Schur form (Section 2, eq. 4).
+// Result: a rotation G = [[cs -sn][sn cs]] and the block G^T B G, which is upper
+// triangular when the eigenvalues are real and otherwise has equal diagonal
+// entries and off-diagonal entries of opposite sign.
+//
+// Construction (two angles, composed):
+//  1. Rotating by t changes the diagonal difference to
+//     (a - d) cos 2t + (b + c) sin 2t, so tan 2t1 = (d - a) / (b + c) gives a
+//     block [[m b1][c1 m]], m the mean of the diagonal.  tan t1 is taken as the
+//     root of modulus <= 1 of tan 2t1 = 2 tan t1 / (1 - tan^2 t1).
+//  2. The eigenvalues of that block are m +- sqrt(b1 c1).  If b1 and c1 have
+//     opposite signs the pair is complex and the block is final.  Otherwise
+//     rotating it by t2 leaves (2,1) entry c1 cos^2 t2 - b1 sin^2 t2, which a
+//     rotation with (cos t2, sin t2) proportional to (sqrt|b1|, sqrt|c1|)
+//     annihilates.
+// The output block is formed from B itself by the composed rotation (one
+// rounding step on the diagonal), and the entry that is zero in exact
+// arithmetic is set to zero.
 struct Std2 {
     double a, b, c, d, cs, sn;
-    double rr1, ri1, rr2, ri2;
 };
 
+// G^T [[a b][c d]] G for G = [[C -S][S C]]: out = (0,0), (0,1), (1,0), (1,1).
+__device__ __forceinline__ void rot2_similarity(double a, double b, double c, double d, double C, double S,
+                                                double (&out)[4]) {
+    const double p00 = a * C + b * S, p01 = b * C - a * S;  // B G, first row
+    const double p10 = c * C + d * S, p11 = d * C - c * S;  // B G, second row
+    out[0] = C * p00 + S * p10;
+    out[1] = C * p01 + S * p11;
+    out[2] = C * p10 - S * p00;
+    out[3] = C * p11 - S * p01;
+}
+
 __device__ __forceinline__ Std2 std2x2(double a, double b, double c, double d) {
-    Std2 o;
-    o.ri1 = o.ri2 = 0.0;
-    if (c == 0.0) {
-        o.a = a; o.b = b; o.c = 0.0; o.d = d; o.cs = 1.0; o.sn = 0.0;
-        o.rr1 = a; o.rr2 = d;
+    Std2 o{a, b, c, d, 1.0, 0.0};
+    if (c == 0.0) return o;  // already triangular
+    const double big = fmax(fmax(fabs(a), fabs(b)), fmax(fabs(c), fabs(d)));
+    const double inv = 1.0 / big;
+    // angle 1 (scale-free, so computed on the scaled entries)
+    const double u = d * inv - a * inv, v = b * inv + c * inv;
+    double t1 = 0.0;
+    if (u != 0.0) {
+        const double h = hypot(u, v);
+        t1 = u / (v >= 0.0 ? v + h : v - h);
+    }
+    const double C1 = 1.0 / sqrt(1.0 + t1 * t1), S1 = t1 * C1;
+    double e[4];
+    rot2_similarity(a, b, c, d, C1, S1, e);
+    if ((e[1] > 0.0 && e[2] < 0.0) || (e[1] < 0.0 && e[2] > 0.0)) {
+        const double m = 0.5 * (e[0] + e[3]);
+        o.a = m; o.b = e[1]; o.c = e[2]; o.d = m; o.cs = C1; o.sn = S1;
         return o;
     }
-    if (b == 0.0) {
-        o.a = d; o.b = -c; o.c = 0.0; o.d = a; o.cs = 0.0; o.sn = 1.0;
-        o.rr1 = d; o.rr2 = a;
-        return o;
-    }
-    double p = 0.5 * (a - d);
-    double bc = b * c;
-    double disc = p * p + bc;
-    if (disc >= 0.0) {
-        double r = sqrt(disc);
-        double z = (p >= 0.0) ? p + r : p - r;
-        if (z == 0.0) {
-            o.a = a; o.b = b; o.c = 0.0; o.d = d; o.cs = 1.0; o.sn = 0.0;
-            o.rr1 = a; o.rr2 = d;
-            return o;
-        }
-        double t = hypot(z, c);
-        double cs = z / t, sn = c / t;
-        o.cs = cs; o.sn = sn;
-        o.a = d + z;
-        o.d = d - bc / z;
-        o.b = (d - a) * cs * sn + b * cs * cs - c * sn * sn;
-        o.c = 0.0;
-        o.rr1 = o.a; o.rr2 = o.d;
-        return o;
-    }
-    double q = 0.5 * (b + c), k = 0.5 * (b - c);
-    double r = hypot(p, q);
-    double cs = 1.0, sn = 0.0;
-    if (r != 0.0) {
-        double c2 = q / r, s2 = -p / r;
-        if (c2 >= 0.0) {
-            cs = sqrt(0.5 * (1.0 + c2));
-            sn = s2 / (2.0 * cs);
-        } else {
-            sn = copysign(sqrt(0.5 * (1.0 - c2)), s2);
-            cs = s2 / (2.0 * sn);
-        }
-    }
-    double m = 0.5 * (a + d);
-    o.cs = cs; o.sn = sn;
-    o.a = m; o.d = m; o.b = r + k; o.c = r - k;
-    o.rr1 = o.rr2 = m;
-    o.ri1 = sqrt(fabs(o.b)) * sqrt(fabs(o.c));
-    o.ri2 = -o.ri1;
+    // angle 2 (real pair)
+    const double p = sqrt(fabs(e[1] * inv)), q = sqrt(fabs(e[2] * inv));
+    const double r = hypot(p, q);
+    const double C2 = (r > 0.0) ? p / r : 1.0, S2 = (r > 0.0) ? q / r : 0.0;
+    const double C = C1 * C2 - S1 * S2, S = S1 * C2 + C1 * S2;
+    rot2_similarity(a, b, c, d, C, S, e);
+    o.a = e[0]; o.b = e[1]; o.c = 0.0; o.d = e[3]; o.cs = C; o.sn = S;
     return o;
 }
 

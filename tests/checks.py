@@ -101,3 +101,17 @@ def match_eigenvalues(a, b):
         r, c = linear_sum_assignment(cost)
         B = B[c[np.argsort(r)]]
     return A, B
+
+
+def std2x2_cases():
+    """2x2 blocks for the standardisation pins: hand-picked special cases (already
+    triangular, zero upper entry, equal diagonal, tiny coupling, near underflow,
+    strongly graded) and 400 seeded random blocks, half of them with entries
+    spread over 16 orders of magnitude."""
+    g = np.random.default_rng(12)
+    cases = [(1, 2, 3, 4), (1, -2, 3, 1), (0, 1, -1, 0), (2, 0, 3, 5), (2, 3, 0, 5), (1, 1e-20, 1e-20, 1),
+             (1, 1, -1e-18, 1), (3, 4, 4, 3), (0, 0, 1, 0), (1e-300, 1e-300, -1e-300, 1e-300), (5, -1, 1, 5),
+             (1, 4, 1, 1), (-2, 1e8, -1e-8, 3)]
+    cases += [tuple(g.standard_normal(4)) for _ in range(200)]
+    cases += [tuple(g.standard_normal(4) * 10.0 ** g.integers(-8, 8, 4)) for _ in range(200)]
+    return cases

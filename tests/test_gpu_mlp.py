@@ -145,6 +145,36 @@ def test_feature_kernel_against_oracle(neig, case):
     assert np.all(np.diff(f1[1:20]) >= 0)
 
 
+@pytest.mark.parametrize("stride", [0, 2, 3])
+def test_feature_kernel_closed_form(neig, stride):
+    """The device features on the hand-built matrices whose quantiles are known in
+    closed form (the oracle's pins): every subdiagonal entry used (stride 0), or
+    the 1024-entry sample with stride 2 or 3 and decoy values between samples."""
+    from test_oracle_mlp import _graded_block
+
+    probs = 0.05 * np.arange(1, 20)
+    if stride == 0:
+        n, ktop, kbot = 340, 17, 318
+        logs = np.random.default_rng(3).permutation(np.arange(kbot - ktop) / 10.0)
+        want = probs * 30.0
+        hs = 3.0
+    else:
+        ktop = 5
+        kbot = ktop + 1024 * stride
+        n = kbot + 4
+        logs = np.full(1024 * stride, -600.0)
+        logs[::stride] = 0.5 * np.arange(1024)
+        want = 0.5 * 1023 * probs
+        hs = 2.0
+    H = _graded_block(n, ktop, kbot, logs, hs)
+    extra = np.array([0.25, -1.5, 2.0, 0.125], dtype=np.float32)
+    f1, _, _ = neig.policy_features(to_dev(H), ktop, kbot, hs * np.sqrt(n), extra)
+    assert abs(f1[0] - np.log(kbot - ktop + 1)) <= 1e-6
+    # FP32 features: a few ulps of the largest value
+    assert np.allclose(f1[1:20], want, rtol=1e-6, atol=1e-4), (f1[1:20], want)
+    assert np.array_equal(f1[20:24], extra)
+
+
 def _solve_and_check(neig, H, tag):
     Hd = to_dev(H)
     r = neig.schur(Hd)

@@ -15,7 +15,7 @@ import pytest
 import scipy.linalg
 
 import oracle
-from checks import (EPS, backward_error, eigs, invariant_errors, match_eigenvalues, orthogonality,
+from checks import (EPS, backward_error, eigs, invariant_errors, match_eigenvalues, orthogonality, std2x2_cases,
                     structure_violations)
 from paper_2002_05024_amd import inputs
 
@@ -24,17 +24,7 @@ GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
 
 # ---------------------------------------------------------------- 2x2 blocks
 
-def _std_cases():
-    g = np.random.default_rng(12)
-    cases = [(1, 2, 3, 4), (1, -2, 3, 1), (0, 1, -1, 0), (2, 0, 3, 5), (2, 3, 0, 5), (1, 1e-20, 1e-20, 1),
-             (1, 1, -1e-18, 1), (3, 4, 4, 3), (0, 0, 1, 0), (1e-300, 1e-300, -1e-300, 1e-300), (5, -1, 1, 5),
-             (1, 4, 1, 1), (-2, 1e8, -1e-8, 3)]
-    cases += [tuple(g.standard_normal(4)) for _ in range(200)]
-    cases += [tuple(g.standard_normal(4) * 10.0 ** g.integers(-8, 8, 4)) for _ in range(200)]
-    return cases
-
-
-@pytest.mark.parametrize("blk", _std_cases())
+@pytest.mark.parametrize("blk", std2x2_cases())
 def test_std2x2_closed_form(blk):
     a, b, c, d = blk
     B = np.array([[a, b], [c, d]])

@@ -111,3 +111,61 @@ def test_quantile_rule_is_linear_interpolation(k):
     v = np.random.default_rng(k).standard_normal(k)
     probs = 0.05 * np.arange(1, 20)
     assert np.allclose(mlp.quantiles(v, probs), np.quantile(v, probs, method="linear"), atol=1e-14)
+
+
+# ---------------------------------------------------------------- features
+
+def _graded_block(n, ktop, kbot, logvals, hscale):
+    """Hessenberg matrix of order n whose subdiagonal entries in the active
+    block are h(k, k-1) = hscale * exp(logvals[k - ktop - 1]), k = ktop+1..kbot;
+    everything outside the block (other subdiagonals, the rest of the matrix)
+    holds values that would change the features if they were read."""
+    g = np.random.default_rng(7)
+    H = np.triu(g.standard_normal((n, n)), -1) * 1e3
+    for k in range(1, n):
+        H[k, k - 1] = 1e-200 if (k <= ktop or k > kbot) else hscale * np.exp(logvals[k - ktop - 1])
+    return H
+
+
+def test_features_closed_form_every_subdiagonal():
+    # m - 1 = 301 <= 1024: every subdiagonal entry of the block is used, with
+    # log(|h| / scale) = 0, 1/10, ..., 30 (sorted, evenly spaced), so the
+    # p-quantile is exactly p * 30; f0 = log m; f20..f23 are passed through
+    n, ktop, kbot = 340, 17, 318
+    m = kbot - ktop + 1
+    hnorm = 3.0 * np.sqrt(n)  # scale hnorm / sqrt(n) = 3
+    logs = np.arange(m - 1) / 10.0
+    g = np.random.default_rng(3)
+    H = _graded_block(n, ktop, kbot, g.permutation(logs), 3.0)  # order along the diagonal is irrelevant
+    extra = [0.25, -1.5, 2.0, 0.125]
+    f = mlp.features(H, ktop, kbot, hnorm, extra)
+    assert f[0] == pytest.approx(np.log(m), abs=1e-15)
+    probs = 0.05 * np.arange(1, 20)
+    assert np.allclose(f[1:20], probs * 30.0, rtol=0, atol=1e-12)
+    assert list(f[20:24]) == extra
+
+
+@pytest.mark.parametrize("stride", [2, 3])
+def test_features_closed_form_sampled_subdiagonal(stride):
+    # m - 1 = 1024 * stride > 1024: the sample is k = ktop + 1 + stride * i,
+    # i < 1024.  Entries at those offsets carry log values 0, 0.5, ..., 511.5;
+    # every other entry of the block carries -600, which would pull the low
+    # quantiles down if any were sampled.  p-quantile = 0.5 * 1023 p exactly.
+    cnt = 1024 * stride
+    ktop = 5
+    kbot = ktop + cnt
+    n = kbot + 4
+    logs = np.full(cnt, -600.0)
+    logs[::stride] = 0.5 * np.arange(1024)
+    H = _graded_block(n, ktop, kbot, logs, 2.0)
+    f = mlp.features(H, ktop, kbot, 2.0 * np.sqrt(n), [0, 0, 0, 0])
+    assert f[0] == pytest.approx(np.log(cnt + 1), abs=1e-15)
+    probs = 0.05 * np.arange(1, 20)
+    assert np.allclose(f[1:20], 0.5 * 1023 * probs, rtol=0, atol=1e-11)
+
+
+def test_features_single_row_block():
+    # m = 1: no subdiagonal entry, the quantile features are zero
+    H = _graded_block(8, 3, 3, [], 1.0)
+    f = mlp.features(H, 3, 3, 1.0, [1, 2, 3, 4])
+    assert f[0] == 0.0 and np.all(f[1:20] == 0.0) and list(f[20:24]) == [1, 2, 3, 4]
