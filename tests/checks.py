@@ -115,3 +115,19 @@ def std2x2_cases():
     cases += [tuple(g.standard_normal(4)) for _ in range(200)]
     cases += [tuple(g.standard_normal(4) * 10.0 ** g.integers(-8, 8, 4)) for _ in range(200)]
     return cases
+
+
+def t_eigs_in_order(T):
+    """Eigenvalues of a standardised quasi-triangular T in diagonal order."""
+    n = T.shape[0]
+    out = np.zeros(n, dtype=complex)
+    j = 0
+    while j < n:
+        if j + 1 < n and T[j + 1, j] != 0:
+            b = np.sqrt(abs(T[j, j + 1] * T[j + 1, j]))
+            out[j], out[j + 1] = T[j, j] + 1j * b, T[j, j] - 1j * b
+            j += 2
+        else:
+            out[j] = T[j, j]
+            j += 1
+    return out

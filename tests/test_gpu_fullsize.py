@@ -12,7 +12,7 @@ import numpy as np
 import pytest
 
 import oracle
-from checks import EPS, eigs, match_eigenvalues, structure_violations
+from checks import EPS, eigs, match_eigenvalues, structure_violations, t_eigs_in_order
 from gpu_util import gpu_backward_error, gpu_orthogonality, say, to_dev, to_host
 from paper_2002_05024_amd import inputs
 
@@ -44,21 +44,6 @@ def prescribed_case(n, std_scale, idx):
     A = np.asfortranarray(U @ T @ U.T)
     H, Q1 = inputs.to_hessenberg(A)
     return T, lam, A, H, Q1
-
-
-def t_eigs_in_order(T):
-    n = T.shape[0]
-    out = np.zeros(n, dtype=complex)
-    j = 0
-    while j < n:
-        if j + 1 < n and T[j + 1, j] != 0:
-            b = np.sqrt(abs(T[j, j + 1] * T[j + 1, j]))
-            out[j], out[j + 1] = T[j, j] + 1j * b, T[j, j] - 1j * b
-            j += 2
-        else:
-            out[j] = T[j, j]
-            j += 1
-    return out
 
 
 @pytest.mark.parametrize("variant", ["well_conditioned", "as_written"])

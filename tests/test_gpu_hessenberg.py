@@ -16,7 +16,7 @@ import numpy as np
 import pytest
 
 import oracle
-from checks import EPS, backward_error, orthogonality, structure_violations
+from checks import EPS, backward_error, eigs, match_eigenvalues, orthogonality, structure_violations, t_eigs_in_order
 from gpu_util import gpu_backward_error, gpu_orthogonality, say, to_dev, to_host
 from paper_2002_05024_amd import inputs
 
@@ -120,7 +120,9 @@ def test_pipeline_prescribed_n4000(neig):
 
     n = 4000
     g = inputs.rng(inputs.PRESCRIBED, 4200)
-    A, lam = inputs.prescribed_matrix(n, g, 0.1 / np.sqrt(n))
+    T, lam = inputs.prescribed_quasi_triangular(n, g, 0.1 / np.sqrt(n))
+    U = inputs.haar_orthogonal(n, g)
+    A = np.asfortranarray(U @ T @ U.T)  # the construction of inputs.prescribed_matrix, T kept
     Ad = to_dev(A)
     A0 = Ad.clone()
     say(f"pipeline n={n}")
@@ -136,8 +138,20 @@ def test_pipeline_prescribed_n4000(neig):
     assert be <= 50 * n * EPS and oe <= 50 * n * EPS
     S = to_host(Ad)
     assert structure_violations(S, r.wr.cpu().numpy(), r.wi.cpu().numpy()) == []
-    got = np.sort_complex(r.wr.cpu().numpy() + 1j * r.wi.cpu().numpy())
-    assert np.abs(got - np.sort_complex(lam)).max() <= 1e-9
+    # eigenvalues against the prescribed ones within 1e-10 ||A||_F cond(lambda);
+    # the condition numbers come from the prescribed T (an input), computed one
+    # by one for the eigenvalues that are not already within 1e-12 ||A||_F
+    lt = t_eigs_in_order(T)
+    X, Y = match_eigenvalues(lt, eigs(r.wr.cpu().numpy(), r.wi.cpu().numpy()))
+    na = np.linalg.norm(A)
+    err = np.abs(X - Y)
+    loose = np.nonzero(err > 1e-12 * na)[0]
+    if loose.size:
+        pos = np.array([int(np.argmin(np.abs(lt - X[k]))) for k in loose])
+        cond = oracle.cond_subset(T, pos)
+        say(f"  {loose.size} eigenvalues beyond 1e-12 ||A||: worst err/(||A|| cond) "
+            f"{np.max(err[loose] / (na * cond)):.2e}")
+        assert np.all(err[loose] <= 1e-10 * na * cond)
 
 
 def test_hessenberg_padded_leading_dimensions(neig):
