@@ -140,6 +140,31 @@ int neig_schur(int n, double *H, int ldh, double *Z, int ldz, double *wr, double
 int neig_schur_batched(int batch, const int *n, double *const *H, const int *ldh, double *const *Z, const int *ldz,
                        double *const *wr, double *const *wi, int *info, hipStream_t stream);
 
+/* Largest batch one neig_schur_batched_noalloc call takes. */
+#define NEIG_BATCH_NOALLOC_MAX 4096
+
+/*
+ * neig_schur_batched_noalloc -- neig_schur_batched for callers that cannot
+ * allocate memory: code under HIP graph capture, tight serving loops, and
+ * harnesses that forbid hipMalloc.  Same arguments, results, asynchrony and
+ * error codes as neig_schur_batched, with the same kernels; it calls no
+ * hipMalloc, hipFree or other allocating routine.  Its only scratch (the
+ * problem descriptors, the processing order and the work counter, about
+ * 213 KB) is a fixed array in device memory that each GPU the library runs on
+ * holds until the process ends; its device address is looked up once per
+ * device on the first call there.
+ *   batch   0 <= batch <= NEIG_BATCH_NOALLOC_MAX; -1 beyond it (nothing runs).
+ * Every call on one GPU uses that GPU's one array: calls (and graph replays)
+ * that overlap in time on the same GPU race and give undefined results; keep
+ * them on one stream.  The array keeps the last call's contents; everything a
+ * call reads from it is rewritten by that call's first kernel.
+ * Returns 0, a negative code as neig_schur_batched, or <= -100 for a HIP error
+ * (also when the array's address cannot be obtained).
+ */
+int neig_schur_batched_noalloc(int batch, const int *n, double *const *H, const int *ldh, double *const *Z,
+                               const int *ldz, double *const *wr, double *const *wi, int *info,
+                               hipStream_t stream);
+
 /* Size classes of the batched solver. */
 #define NEIG_BATCH_CLASSES 6
 

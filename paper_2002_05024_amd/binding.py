@@ -103,6 +103,8 @@ def load_library():
     lib.neig_schur.restype = _i
     lib.neig_schur_batched.argtypes = [_i, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp]
     lib.neig_schur_batched.restype = _i
+    lib.neig_schur_batched_noalloc.argtypes = [_i, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp]
+    lib.neig_schur_batched_noalloc.restype = _i
     _fp = ctypes.POINTER(ctypes.c_float)
     sigs = {
         "neig_policy_bins": [_ip, _ip],
@@ -298,15 +300,18 @@ def batched_tables(Hs, Zs=None):
     return BatchedCall(Hs, Zs, wrs, wis, info, meta, ptrs)
 
 
-def launch_batched(call, stream=None) -> None:
-    """Enqueue neig_schur_batched for the tables of ``call`` (asynchronous)."""
+def launch_batched(call, stream=None, noalloc: bool = False) -> None:
+    """Enqueue neig_schur_batched (or, with ``noalloc``, the entry point that
+    allocates nothing, neig_schur_batched_noalloc) for the tables of ``call``
+    (asynchronous)."""
     lib = load_library()
     b = len(call.Hs)
     m, p = call.meta.data_ptr(), call.ptrs.data_ptr()
     vp = ctypes.c_void_p
-    rc = lib.neig_schur_batched(b, vp(m), vp(p), vp(m + 4 * b), vp(p + 8 * b), vp(m + 8 * b), vp(p + 16 * b),
-                                vp(p + 24 * b), vp(call.info.data_ptr()), _stream_ptr(stream))
-    _raise("neig_schur_batched", rc)
+    name = "neig_schur_batched_noalloc" if noalloc else "neig_schur_batched"
+    rc = getattr(lib, name)(b, vp(m), vp(p), vp(m + 4 * b), vp(p + 8 * b), vp(m + 8 * b), vp(p + 16 * b),
+                            vp(p + 24 * b), vp(call.info.data_ptr()), _stream_ptr(stream))
+    _raise(name, rc)
 
 
 def schur_batched(Hs, Zs=None, stream=None):
@@ -316,6 +321,14 @@ def schur_batched(Hs, Zs=None, stream=None):
     per-problem info tensor."""
     call = batched_tables(Hs, Zs)
     launch_batched(call, stream)
+    return call
+
+
+def schur_batched_noalloc(Hs, Zs=None, stream=None):
+    """As :func:`schur_batched`, through neig_schur_batched_noalloc (at most
+    NEIG_BATCH_NOALLOC_MAX problems; the library allocates nothing)."""
+    call = batched_tables(Hs, Zs)
+    launch_batched(call, stream, noalloc=True)
     return call
 
 

@@ -149,24 +149,41 @@ void allow_dynamic_lds(const void *fn, size_t lds_max) {
     (void)hipGetLastError();
 }
 
+// LDS per workgroup, the largest orders the LDS kernels take with it, and the
+// compute-unit count of device dev.
+struct DevLimits {
+    size_t lds_max;
+    int small_max, chase_max, cus;
+};
+
+DevLimits device_limits(int dev) {
+    DevLimits d;
+    int lds = 0;
+    ck(hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
+    d.lds_max = (size_t)lds;
+    int m = NEIG_SMALL_MAX;
+    while (m > 4 && (size_t)(2 * m * (m + 1) + m) * 8 > d.lds_max) --m;
+    d.small_max = m;
+    int c = NEIG_CHASE_MAX;
+    while (c > 8 && (size_t)(2 * (c + 1) * (c + 2)) * 8 + 2048 > d.lds_max) --c;
+    d.chase_max = c;
+    ck(hipDeviceGetAttribute(&d.cus, hipDeviceAttributeMultiprocessorCount, dev));
+    return d;
+}
+
 DeviceWs &workspace() {
     int dev = 0;
     ck(hipGetDevice(&dev));
     DeviceWs &w = g_ws[dev];
     if (w.ready) return w;
-    int lds = 0;
-    ck(hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
-    w.lds_max = (size_t)lds;
-    int m = NEIG_SMALL_MAX;
-    while (m > 4 && (size_t)(2 * m * (m + 1) + m) * 8 > w.lds_max) --m;
-    w.small_max = m;
-    int c = NEIG_CHASE_MAX;
-    while (c > 8 && (size_t)(2 * (c + 1) * (c + 2)) * 8 + 2048 > w.lds_max) --c;
-    w.chase_max = c;
+    const DevLimits lim = device_limits(dev);
+    w.lds_max = lim.lds_max;
+    w.small_max = lim.small_max;
+    w.chase_max = lim.chase_max;
     for (const void *fn : {(const void *)k_small_qr, (const void *)k_aed, (const void *)k_chase,
                            (const void *)k_update, (const void *)k_batched, (const void *)k_reorder_window})
         allow_dynamic_lds(fn, w.lds_max);
-    ck(hipDeviceGetAttribute(&w.cus, hipDeviceAttributeMultiprocessorCount, dev));
+    w.cus = lim.cus;
     ck(hipMalloc((void **)&w.ist, kStatusInts * sizeof(int)));
     ck(hipMalloc((void **)&w.bprob, (size_t)NEIG_BATCH_MAX * sizeof(BProb)));
     ck(hipMalloc((void **)&w.border, (size_t)NEIG_BATCH_MAX * sizeof(int)));
@@ -1229,10 +1246,11 @@ extern "C" int neig_aed(int n, double *H, int ldh, double *Z, int ldz, int ktop,
     }
 }
 
-extern "C" int neig_schur_batched(int batch, const int *n, double *const *H, const int *ldh, double *const *Z,
-                                  const int *ldz, double *const *wr, double *const *wi, int *info,
-                                  hipStream_t stream) {
-    if (batch < 0 || batch > NEIG_BATCH_MAX) return -1;
+namespace {
+
+int check_batched_args(int batch, int cap, const int *n, double *const *H, const int *ldh, double *const *Z,
+                       const int *ldz, double *const *wr, double *const *wi, int *info) {
+    if (batch < 0 || batch > cap) return -1;
     if (batch == 0) return 0;
     if (!n) return -2;
     if (!H) return -3;
@@ -1242,36 +1260,117 @@ extern "C" int neig_schur_batched(int batch, const int *n, double *const *H, con
     if (!wr) return -7;
     if (!wi) return -8;
     if (!info) return -9;
+    return 0;
+}
+
+// The launch pair of the batched solver: descriptors, order and counter live in
+// the buffers the caller of this function provides (library workspace, or the
+// fixed array of the no-allocation entry point).
+void launch_batched_pair(int batch, const int *n, double *const *H, const int *ldh, double *const *Z,
+                         const int *ldz, double *const *wr, double *const *wi, int *info, BProb *probs, int *order,
+                         int *next, int small_max, int chase_max, int cus, hipStream_t stream) {
+    hipLaunchKernelGGL(k_batched_pack, dim3((batch + 255) / 256), dim3(256), 0, stream, probs, order, next, info, n,
+                       ldh, ldz, H, Z, wr, wi, batch);
+    ck(hipGetLastError());
+    BArgs A;
+    std::memset(&A, 0, sizeof(A));
+    A.probs = probs;
+    A.order = order;
+    A.nprob = batch;
+    A.next = next;
+    A.info = info;
+    for (int k = 0; k < B_NBUCKET; ++k) {
+        A.bucket_hi[k] = g_btab.hi[k];
+        A.tune[k] = g_btab.t[k];
+        A.tune[k].nw = std::min(A.tune[k].nw, small_max);
+        A.tune[k].nmin = std::min(A.tune[k].nmin, small_max);
+        A.tune[k].wchase = std::min(A.tune[k].wchase, chase_max);
+        A.tune[k].ns = std::min(A.tune[k].ns, 2 * B_MAX_BULGES);
+    }
+    A.criterion = g_params.deflation;
+    A.nibble = g_params.nibble > 0 ? g_params.nibble : 14;
+    A.exc = g_params.exc > 0 ? g_params.exc : 6;
+    A.maxit_factor = 30;
+    const int grid = std::max(1, std::min(batch, cus > 0 ? cus : 256));
+    const size_t lds = (size_t)(NEIG_CHASE_MAX + 1) * (NEIG_CHASE_MAX + 2) * sizeof(double) +
+                       (size_t)NEIG_CHASE_MAX * (NEIG_CHASE_MAX + 1) * sizeof(double);
+    hipLaunchKernelGGL(k_batched, dim3(grid), dim3(NT), lds, stream, A);
+    ck(hipGetLastError());
+}
+
+}  // namespace
+
+extern "C" int neig_schur_batched(int batch, const int *n, double *const *H, const int *ldh, double *const *Z,
+                                  const int *ldz, double *const *wr, double *const *wi, int *info,
+                                  hipStream_t stream) {
+    const int a = check_batched_args(batch, NEIG_BATCH_MAX, n, H, ldh, Z, ldz, wr, wi, info);
+    if (a || batch == 0) return a;
     std::lock_guard<std::mutex> lock(g_mutex);
     try {
         DeviceWs &ws = workspace();
-        hipLaunchKernelGGL(k_batched_pack, dim3((batch + 255) / 256), dim3(256), 0, stream, ws.bprob, ws.border,
-                           ws.bnext, info, n, ldh, ldz, H, Z, wr, wi, batch);
-        ck(hipGetLastError());
-        BArgs A;
-        std::memset(&A, 0, sizeof(A));
-        A.probs = ws.bprob;
-        A.order = ws.border;
-        A.nprob = batch;
-        A.next = ws.bnext;
-        A.info = info;
-        for (int k = 0; k < B_NBUCKET; ++k) {
-            A.bucket_hi[k] = g_btab.hi[k];
-            A.tune[k] = g_btab.t[k];
-            A.tune[k].nw = std::min(A.tune[k].nw, ws.small_max);
-            A.tune[k].nmin = std::min(A.tune[k].nmin, ws.small_max);
-            A.tune[k].wchase = std::min(A.tune[k].wchase, ws.chase_max);
-            A.tune[k].ns = std::min(A.tune[k].ns, 2 * B_MAX_BULGES);
-        }
-        A.criterion = g_params.deflation;
-        A.nibble = g_params.nibble > 0 ? g_params.nibble : 14;
-        A.exc = g_params.exc > 0 ? g_params.exc : 6;
-        A.maxit_factor = 30;
-        const int grid = std::max(1, std::min(batch, ws.cus > 0 ? ws.cus : 256));
-        const size_t lds = (size_t)(NEIG_CHASE_MAX + 1) * (NEIG_CHASE_MAX + 2) * sizeof(double) +
-                           (size_t)NEIG_CHASE_MAX * (NEIG_CHASE_MAX + 1) * sizeof(double);
-        hipLaunchKernelGGL(k_batched, dim3(grid), dim3(NT), lds, stream, A);
-        ck(hipGetLastError());
+        launch_batched_pair(batch, n, H, ldh, Z, ldz, wr, wi, info, ws.bprob, ws.border, ws.bnext, ws.small_max,
+                            ws.chase_max, ws.cus, stream);
+    } catch (const HipFail &f) {
+        return -100 - (int)f.e;
+    }
+    return 0;
+}
+
+// ---------------------------------------------------------------- no-allocation batched entry
+//
+// The descriptor table, order and work counter of neig_schur_batched_noalloc
+// live in this fixed device array.  In host code its name is only a stand-in for
+// the symbol: the device address of each GPU's copy comes from
+// hipGetSymbolAddress, once per device, and only that address is passed on.
+namespace {
+constexpr size_t kNaOrderOff = ((size_t)NEIG_BATCH_NOALLOC_MAX * sizeof(BProb) + 255) & ~(size_t)255;
+constexpr size_t kNaNextOff = kNaOrderOff + (((size_t)NEIG_BATCH_NOALLOC_MAX * sizeof(int) + 255) & ~(size_t)255);
+constexpr size_t kNaBytes = kNaNextOff + 256;
+}  // namespace
+
+static __device__ __align__(256) unsigned char scratch[kNaBytes];
+
+namespace {
+
+struct NoAllocDev {
+    bool ready = false;
+    unsigned char *ptr = nullptr;  // device address of this GPU's scratch
+    int small_max = 0, chase_max = 0, cus = 0;
+};
+NoAllocDev g_na[kMaxDevices];
+
+// Set-up on the current device (no allocation): the scratch address, the LDS
+// limits and the compute-unit count.
+NoAllocDev &noalloc_device() {
+    int dev = 0;
+    ck(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDevices) throw HipFail{hipErrorInvalidDevice};
+    NoAllocDev &d = g_na[dev];
+    if (d.ready) return d;
+    void *ptr = nullptr;
+    ck(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+    const DevLimits lim = device_limits(dev);
+    allow_dynamic_lds((const void *)k_batched, lim.lds_max);
+    d.ptr = (unsigned char *)ptr;
+    d.small_max = lim.small_max;
+    d.chase_max = lim.chase_max;
+    d.cus = lim.cus;
+    d.ready = true;
+    return d;
+}
+
+}  // namespace
+
+extern "C" int neig_schur_batched_noalloc(int batch, const int *n, double *const *H, const int *ldh,
+                                          double *const *Z, const int *ldz, double *const *wr, double *const *wi,
+                                          int *info, hipStream_t stream) {
+    const int a = check_batched_args(batch, NEIG_BATCH_NOALLOC_MAX, n, H, ldh, Z, ldz, wr, wi, info);
+    if (a || batch == 0) return a;
+    std::lock_guard<std::mutex> lock(g_mutex);
+    try {
+        NoAllocDev &d = noalloc_device();
+        launch_batched_pair(batch, n, H, ldh, Z, ldz, wr, wi, info, (BProb *)d.ptr, (int *)(d.ptr + kNaOrderOff),
+                            (int *)(d.ptr + kNaNextOff), d.small_max, d.chase_max, d.cus, stream);
     } catch (const HipFail &f) {
         return -100 - (int)f.e;
     }

@@ -101,6 +101,11 @@ def test_batched_argument_errors_without_gpu_work():
     assert lib.neig_schur_batched(65537, *([None] * 9)) == -1
     assert lib.neig_schur_batched(0, *([None] * 9)) == 0
     assert lib.neig_schur_batched(3, *([None] * 9)) == -2
+    lib.neig_schur_batched_noalloc.argtypes = [ctypes.c_int] + [ctypes.c_void_p] * 9
+    assert lib.neig_schur_batched_noalloc(-1, *([None] * 9)) == -1
+    assert lib.neig_schur_batched_noalloc(4097, *([None] * 9)) == -1  # above its fixed capacity
+    assert lib.neig_schur_batched_noalloc(0, *([None] * 9)) == 0
+    assert lib.neig_schur_batched_noalloc(3, *([None] * 9)) == -2
 
 
 def test_product_path_has_no_cpu_fallback():
