@@ -44,7 +44,8 @@ def parse():
     ap.add_argument("--timing", type=int, default=1, help="per-kernel HIP event timing inside the library")
     ap.add_argument("--check", type=int, default=1, help="backward error / orthogonality of the last step")
     ap.add_argument("--cpu-baseline", type=int, default=1)
-    ap.add_argument("--cpu-n", type=int, default=1800, help="order of the oracle's bounded CPU sample")
+    ap.add_argument("--cpu-n", type=str, default="500,1000,2000",
+                    help="orders of the oracle's bounded CPU samples (a n^3 is fitted to them)")
     ap.add_argument("--batched", type=int, default=1, help="also run the batched workload")
     ap.add_argument("--batch-count", type=int, default=512)
     ap.add_argument("--batch-steps", type=int, default=3)
@@ -56,6 +57,10 @@ def parse():
                     help="order of the dense matrix for the Hessenberg-reduction leg (0 skips it)")
     ap.add_argument("--learned", type=int, default=9,
                     help="held-out matrices (n in [1000, 3000]) for the proposal-network leg (0 skips it)")
+    ap.add_argument("--plain256", type=int, default=1,
+                    help="the n=256 plain workload: GPU and oracle (one core), median of 5")
+    ap.add_argument("--prescribed", type=int, default=4000,
+                    help="order of the prescribed-spectrum leg (as written and well-conditioned; 0 skips it)")
     return ap.parse_args()
 
 
@@ -96,25 +101,35 @@ def backward_and_orth(H0, S, Z):
     return be, oe
 
 
-def cpu_baseline(n_sample, n_target):
-    """The oracle (plain single-threaded C, double-shift Francis QR) on a bounded
-    sample of the same workload, scaled to the target order by n^3."""
+def cpu_baseline(samples, n_target):
+    """The oracle (plain single-threaded C, double-shift Francis QR) on bounded
+    samples of the same workload -- one random N(0,1) Hessenberg matrix per order
+    in ``samples`` -- with t = a n^3 fitted to them (least squares) and
+    evaluated at the target order."""
+    import numpy as np
+
     import oracle
     from paper_2002_05024_amd import inputs
 
     oracle.build() if not os.path.exists(os.path.join(ROOT, "oracle", "liboracle.so")) else None
-    H = inputs.random_hessenberg(n_sample, inputs.rng(inputs.FULL, 1000 + n_sample))
-    t0 = time.perf_counter()
-    S, Z, wr, wi, info = oracle.schur(H)
-    dt = time.perf_counter() - t0
-    scale = (n_target / n_sample) ** 3
+    ns, ts = [], []
+    for n_sample in samples:
+        H = inputs.random_hessenberg(n_sample, inputs.rng(inputs.FULL, 1000 + n_sample))
+        t0 = time.perf_counter()
+        S, Z, wr, wi, info = oracle.schur(H)
+        ts.append(time.perf_counter() - t0)
+        ns.append(n_sample)
+        print(f"[bench] oracle n={n_sample} {ts[-1]:.2f}s info={info}", file=sys.stderr, flush=True)
+    x = np.array(ns, dtype=float) ** 3
+    a = float(np.dot(x, ts) / np.dot(x, x))
     return {
-        "value": dt * scale,
+        "value": a * n_target ** 3,
         "unit": "s",
         "cores": 1,
         "kind": "oracle",
-        "sample": f"one random N(0,1) Hessenberg matrix of order {n_sample} solved in {dt:.2f} s "
-                  f"(info={info}); value = that time x ({n_target}/{n_sample})^3",
+        "sample": "one random N(0,1) Hessenberg matrix per order "
+                  + ", ".join(f"n={k}: {t:.2f} s" for k, t in zip(ns, ts))
+                  + f"; value = a n^3 at n={n_target} with a = {a:.3e} s fitted by least squares (an extrapolation)",
     }
 
 
@@ -156,7 +171,9 @@ def rooflines(stats):
     form), k_update 2 w^2 len flops per task, k_chase the bytes of its windows
     (load and store of the window of H, store of U)."""
     aed_ms = sum(s["gpu_aed_ms"] for s in stats)
-    aed_n = sum(s["aeds"] for s in stats)
+    # k_aed launches: AED windows solved in LDS, including those inside the
+    # recursive solves of wide windows
+    aed_n = sum(s["aeds"] - s["rec_aeds"] + s["rec_inner_aeds"] for s in stats)
     aed_fl = sum(s["aed_flops"] for s in stats)
     upd_ms = sum(s["gpu_update_ms"] for s in stats)
     upd_n = sum(s["n_update"] for s in stats)
@@ -182,9 +199,121 @@ def rooflines(stats):
             "avg_launch_us": round(upd_ms * 1000.0 / max(upd_n, 1), 2),
             "flops_per_launch": round(upd_fl / max(upd_n, 1), 1),
         }
+    ch_ms = sum(s["gpu_chase_ms"] for s in stats)
+    ch_n = sum(s["n_chase"] for s in stats)
+    ch_b = sum(s["chase_bytes"] for s in stats)
+    if ch_ms > 0:
+        ach = ch_b / (ch_ms / 1000.0) / 1e9
+        out["roofline_chase"] = {
+            "kernel": "k_chase", "bound": "hbm", "achieved": round(ach, 2), "peak": HBM_PEAK_GBS,
+            "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 5),
+            "traffic": traffic_per_launch("k_chase"),
+            "avg_launch_us": round(ch_ms * 1000.0 / max(ch_n, 1), 1),
+            "bytes_per_launch": round(ch_b / max(ch_n, 1), 1),
+            "note": "latency-bound window chase (dependent bulge steps in LDS); HBM is not its limit",
+        }
     dominant = "roofline_aed" if aed_ms >= upd_ms else "roofline_update"
     if dominant in out:
         out["roofline"] = dict(out[dominant])
+    return out
+
+
+def timed_solve(H0, dev, reps):
+    """Median GPU seconds of neig_schur on a copy of H0 (events on the current
+    stream, Z from I; H restored and Z reset untimed before each run) after one
+    warm-up, with the last run's stats and result."""
+    import torch
+
+    from paper_2002_05024_amd import binding
+
+    n = H0.shape[0]
+    H = torch.empty_like(H0)
+    Z = torch.empty_like(H0)
+    times, stats, r = [], [], None
+    for k in range(reps + 1):
+        H.copy_(H0)
+        Z.zero_()
+        Z.diagonal().fill_(1.0)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        r = binding.schur(H, Z)
+        e1.record()
+        torch.cuda.synchronize()
+        if r.info != 0:
+            raise SystemExit(f"n={n}: info={r.info}")
+        if k > 0:
+            times.append(e0.elapsed_time(e1) / 1000.0)
+            stats.append(binding.get_stats())
+    times.sort()
+    return times[len(times) // 2], stats[-1], H, Z, r
+
+
+def plain256_leg(args, dev):
+    """The plain n = 256 workload (random N(0,1) Hessenberg, seed 0, Z from I):
+    GPU median of 5 after one warm-up, and the oracle on one host core, median
+    of 5, beside it."""
+    import numpy as np
+    import torch
+
+    import oracle
+    from paper_2002_05024_amd import inputs
+
+    n = 256
+    H = inputs.random_hessenberg(n, inputs.rng(inputs.PLAIN, 0))
+    H0 = torch.from_numpy(np.ascontiguousarray(H.T)).to(dev).t()
+    sec, st, S, Z, _ = timed_solve(H0, dev, 5)
+    be, oe = backward_and_orth(H0, S, Z)
+    tc = []
+    for _ in range(5):
+        t0 = time.perf_counter()
+        oracle.schur(H)
+        tc.append(time.perf_counter() - t0)
+    tc.sort()
+    return {"workload": "random N(0,1) Hessenberg, n=256, Z from I", "gpu_s": round(sec, 5),
+            "oracle_s_one_core": round(tc[2], 4), "gpu_over_oracle_speedup": round(tc[2] / sec, 2),
+            "aeds": st["aeds"], "small_solves": st["small_solves"],
+            "check": {"backward_error": be, "orthogonality": oe, "bound_50n_eps": 50 * n * 2.0 ** -52}}
+
+
+def prescribed_leg(args, dev):
+    """The prescribed-spectrum workload: A = U T U^T with 2000 eigenvalues in the
+    unit disk (half as conjugate pairs), in Hessenberg form, Z from I; once with
+    the strictly upper part of T drawn with standard deviation 0.1 (as written)
+    and once with 0.1/sqrt(n) (well-conditioned).  Seconds (median of 3) and the
+    method's algorithmic GFLOP/s; the well-conditioned case's eigenvalues are
+    checked against the prescribed ones."""
+    import numpy as np
+    import torch
+
+    from paper_2002_05024_amd import inputs
+
+    n = args.prescribed
+    out = {}
+    for tag, std, idx in (("as_written_std_0.1", 0.1, 4200), ("well_conditioned_std_0.1_over_sqrt_n",
+                                                              0.1 / np.sqrt(n), 4201)):
+        t0 = time.perf_counter()
+        H, lam = inputs.prescribed_hessenberg(n, inputs.rng(inputs.PRESCRIBED, idx), std)
+        print(f"[bench] prescribed {tag} n={n} input in {time.perf_counter() - t0:.1f}s", file=sys.stderr,
+              flush=True)
+        H0 = torch.from_numpy(np.ascontiguousarray(H.T)).to(dev).t()
+        sec, st, S, Z, r = timed_solve(H0, dev, 3)
+        be, oe = backward_and_orth(H0, S, Z)
+        rec = {"seconds": round(sec, 4), "gflops_algorithmic": round(st["alg_flops"] / sec / 1e9, 1),
+               "aeds": st["aeds"], "sweeps": st["sweeps"],
+               "check": {"backward_error": be, "orthogonality": oe, "bound_50n_eps": 50 * n * 2.0 ** -52}}
+        if std < 0.1:  # well-conditioned: every eigenvalue against the prescribed spectrum
+            got = r.wr.cpu().numpy() + 1j * r.wi.cpu().numpy()
+
+            def key(z):
+                return z[np.lexsort((np.sign(z.imag), np.abs(z.imag), z.real))]
+
+            rec["max_eigenvalue_error_vs_prescribed"] = float(np.max(np.abs(key(got) - key(np.asarray(lam)))))
+        out[tag] = rec
+        del H0, S, Z
+        torch.cuda.empty_cache()
+    out["workload"] = (f"prescribed spectrum, n={n}: {n - 2 * (n // 4)} real eigenvalues and {n // 4} conjugate "
+                       "pairs in the unit disk, Hessenberg form, Z from I")
     return out
 
 
@@ -394,6 +523,10 @@ def main():
     if not args.single:
         line = {"metric": "Schur reduction seconds + FP64 GFLOP/s at n=20000; batched solves/sec",
                 "n_gpus": 1, "dtype": "f64", "data": "synthetic"}
+        if args.plain256:
+            line["plain256"] = plain256_leg(args, dev)
+        if args.prescribed:
+            line["prescribed"] = prescribed_leg(args, dev)
         if args.batched:
             line["batched"] = batched_leg(args, dev)
         if args.reorder:
@@ -480,9 +613,13 @@ def main():
     if args.check:
         be, oe = backward_and_orth(H0, H, Z)
         line["check"] = {"backward_error": be, "orthogonality": oe, "bound_50n_eps": 50 * n * 2.0 ** -52}
-    if args.batched or args.reorder or args.hessenberg or args.learned:
+    if args.batched or args.reorder or args.hessenberg or args.learned or args.plain256 or args.prescribed:
         del H, Z, H0
         torch.cuda.empty_cache()
+    if args.plain256:
+        line["plain256"] = plain256_leg(args, dev)
+    if args.prescribed:
+        line["prescribed"] = prescribed_leg(args, dev)
     if args.batched:
         line["batched"] = batched_leg(args, dev)
     if args.reorder:
@@ -492,7 +629,7 @@ def main():
     if args.learned:
         line["learned"] = learned_leg(args, dev)
     if args.cpu_baseline:
-        line["cpu_baseline"] = cpu_baseline(args.cpu_n, n)
+        line["cpu_baseline"] = cpu_baseline([int(v) for v in args.cpu_n.split(",") if v], n)
     print(json.dumps(line), flush=True)
 
 

@@ -67,8 +67,16 @@ typedef struct neig_params {
                          hold for the whole call (the default rules when no network is
                          installed or it is not confident); that decision is logged   */
     int seed;      /* seed of the exploration generator                                  */
-    int reserved[4];
+    int rec_nw;    /* deflation window used inside a recursively solved AED window
+                      (nw > 96; at most 96); 0: the default rule for the window's order */
+    int rec_ns;    /* shifts per sweep inside a recursively solved AED window            */
+    int reserved[2];
 } neig_params;
+
+/* Largest AED window.  Windows of at most 96 rows are solved in one workgroup's
+ * LDS; larger ones (Section 3.2: the window's Schur form by a recursive
+ * application of the QR algorithm) by the whole method run on the window. */
+#define NEIG_AED_MAX 384
 
 /* Counters and timings of the most recent neig_schur call. */
 typedef struct neig_stats {
@@ -87,7 +95,14 @@ typedef struct neig_stats {
     double aed_qr_iters, aed_swaps, aed_cyc_qr, aed_cyc_defl, aed_cyc_hess;
     double aed_late;     /* deflations found above a block that failed the spike test */
     double policy_used, policy_fallback;  /* proposals taken from the network / the default rules */
-    double aed_flops;    /* algorithmic flops of the AED windows alone: 10 nw^3 per AED launch */
+    double aed_flops;    /* algorithmic flops of the LDS AED kernel's windows: 10 nw^3 per launch,
+                            including the launches inside recursive window solves          */
+    /* AED windows of more than 96 rows: how many, the AED steps and sweeps of the
+       recursive solves of those windows (not counted in aeds / sweeps above), and
+       the GPU time (timing = 1) of their deflation kernel */
+    double rec_aeds, rec_inner_aeds, rec_inner_sweeps, gpu_rec_defl_ms;
+    double chase_bytes;  /* algorithmic bytes of the chase windows: 8 (2 mb^2 + w^2) per window
+                            (its block of H loaded and stored, its factor stored)            */
 } neig_stats;
 
 /*

@@ -41,7 +41,9 @@ class Params(ctypes.Structure):
         ("timing", _i),
         ("policy", _i),
         ("seed", _i),
-        ("reserved", _i * 4),
+        ("rec_nw", _i),
+        ("rec_ns", _i),
+        ("reserved", _i * 2),
     ]
 
 
@@ -79,6 +81,11 @@ class Stats(ctypes.Structure):
         ("policy_used", ctypes.c_double),
         ("policy_fallback", ctypes.c_double),
         ("aed_flops", ctypes.c_double),
+        ("rec_aeds", ctypes.c_double),
+        ("rec_inner_aeds", ctypes.c_double),
+        ("rec_inner_sweeps", ctypes.c_double),
+        ("gpu_rec_defl_ms", ctypes.c_double),
+        ("chase_bytes", ctypes.c_double),
     ]
 
 

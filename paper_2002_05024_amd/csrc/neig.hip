@@ -17,6 +17,7 @@
 #include "neig.h"
 
 #include "small.hip"
+#include "aedwide.hip"
 #include "chase.hip"
 #include "gemm.hip"
 #include "util.hip"
@@ -107,6 +108,7 @@ struct DeviceWs {
     double *poly = nullptr; size_t poly_cap = 0;  // bulge polynomials (tr, det)
     double *dbuf = nullptr; size_t dbuf_cap = 0;  // shifts, gathers, norm partials
     double *rot = nullptr; size_t rot_cap = 0;
+    double *aw = nullptr; size_t aw_cap = 0;      // wide AED window: T, V, V^T, vectors
     int *ist = nullptr;                           // device status ints
     int *flag = nullptr; size_t flag_cap = 0;
     int *h_ist = nullptr; size_t h_ist_cap = 0;   // pinned mirrors
@@ -181,7 +183,8 @@ DeviceWs &workspace() {
     w.small_max = lim.small_max;
     w.chase_max = lim.chase_max;
     for (const void *fn : {(const void *)k_small_qr, (const void *)k_aed, (const void *)k_chase,
-                           (const void *)k_update, (const void *)k_batched, (const void *)k_reorder_window})
+                           (const void *)k_update, (const void *)k_update_wide, (const void *)k_batched,
+                           (const void *)k_reorder_window})
         allow_dynamic_lds(fn, w.lds_max);
     w.cus = lim.cus;
     ck(hipMalloc((void **)&w.ist, kStatusInts * sizeof(int)));
@@ -198,7 +201,8 @@ DeviceWs &workspace() {
 
 void free_workspace(DeviceWs &w) {
     if (!w.ready) return;
-    for (void *p : {(void *)w.ut, (void *)w.vt, (void *)w.poly, (void *)w.dbuf, (void *)w.rot, (void *)w.ist,
+    for (void *p : {(void *)w.ut, (void *)w.vt, (void *)w.poly, (void *)w.dbuf, (void *)w.rot, (void *)w.aw,
+                    (void *)w.ist,
                     (void *)w.flag, (void *)w.bprob, (void *)w.border, (void *)w.bnext,
                     (void *)w.theta, (void *)w.pol_out, (void *)w.mlp_part, (void *)w.hrd, (void *)w.hrd_st,
                     (void *)w.rwin, (void *)w.rstat})
@@ -223,8 +227,11 @@ double now_ms() {
 class Solver {
   public:
     Solver(int n, double *H, int ldh, double *Z, int ldz, hipStream_t st)
+        : Solver(n, H, ldh, Z, ldz, st, g_params) {}
+
+    Solver(int n, double *H, int ldh, double *Z, int ldz, hipStream_t st, const neig_params &prm)
         : n_(n), H_(H), ldh_(ldh), Z_(Z), ldz_(ldz), st_(st), ws_(workspace()) {
-        p_ = g_params;
+        p_ = prm;
         nsmall_ = ws_.small_max;
         nmin_ = p_.nmin > 0 ? std::min(p_.nmin, nsmall_) : nsmall_;
         wchase_ = p_.chase_w > 0 ? std::min(p_.chase_w, ws_.chase_max) : ws_.chase_max;
@@ -240,7 +247,7 @@ class Solver {
     neig_stats stats_;
 
     // ---- timing mode: HIP events around launches, per kernel class ---------
-    enum Kind { kUpdate = 0, kChase = 1, kAed = 2, kSmall = 3, kOther = 4 };
+    enum Kind { kUpdate = 0, kChase = 1, kAed = 2, kSmall = 3, kOther = 4, kRecDefl = 5 };
     struct Mark {
         int kind;
         hipEvent_t a, b;
@@ -285,6 +292,7 @@ class Solver {
                 case kChase: stats_.gpu_chase_ms += ms; stats_.n_chase += 1; break;
                 case kAed: stats_.gpu_aed_ms += ms; break;
                 case kSmall: stats_.gpu_small_ms += ms; break;
+                case kRecDefl: stats_.gpu_rec_defl_ms += ms; break;
                 default: stats_.gpu_other_ms += ms; break;
             }
         }
@@ -340,7 +348,10 @@ class Solver {
         int ldc, ldu, w, len, side;
     };
 
-    void run_updates(const std::vector<Task> &tasks) {
+    void run_updates(const std::vector<Task> &all) {
+        std::vector<Task> tasks, wide;
+        for (const Task &t : all) (t.w > UPD_WMAX ? wide : tasks).push_back(t);
+        run_updates_wide(wide);
         size_t i = 0;
         while (i < tasks.size()) {
             UpdArgs a;
@@ -364,6 +375,37 @@ class Solver {
             if (any_left) lds += (size_t)(wmaxp + 1) * UPD_SLICE * sizeof(double);
             timed(kUpdate, [&] {
                 hipLaunchKernelGGL(k_update, dim3(tiles), dim3(UPD_THREADS), lds, st_, a);
+                ck(hipGetLastError());
+            });
+        }
+    }
+
+    // tasks with factors of order UPD_WMAX+1 .. UPW_WMAX: U^T streamed from L2,
+    // only the strip's slice staged in LDS
+    void run_updates_wide(const std::vector<Task> &tasks) {
+        size_t i = 0;
+        while (i < tasks.size()) {
+            UpdArgs a;
+            std::memset(&a, 0, sizeof(a));
+            int tiles = 0, nt = 0, wmaxp = 64;
+            for (; i < tasks.size() && nt < UPD_MAX_TASKS; ++i) {
+                const Task &t = tasks[i];
+                if (t.len <= 0 || t.w <= 0) continue;
+                if (t.w > UPW_WMAX) throw HipFail{hipErrorInvalidValue};
+                UpdTask &u = a.t[nt++];
+                u.C = t.C; u.Ut = t.Ut; u.ldc = t.ldc; u.ldu = t.ldu; u.w = t.w; u.len = t.len; u.side = t.side;
+                u.tile0 = tiles;
+                tiles += (t.len + UPW_SLICE - 1) / UPW_SLICE;
+                wmaxp = std::max(wmaxp, (t.w + 63) & ~63);
+                stats_.gemm_flops += 2.0 * t.w * (double)t.w * t.len;
+            }
+            a.ntask = nt;
+            if (nt == 0 || tiles == 0) continue;
+            // side 0 stages wp x UPW_SLICE with leading dimension wp + 1, side 1
+            // UPW_SLICE x wp with leading dimension UPW_SLICE + 1
+            const size_t lds = (size_t)(wmaxp + 1) * (UPW_SLICE + 1) * sizeof(double);
+            timed(kUpdate, [&] {
+                hipLaunchKernelGGL(k_update_wide, dim3(tiles), dim3(UPW_THREADS), lds, st_, a);
                 ck(hipGetLastError());
             });
         }
@@ -407,9 +449,10 @@ class Solver {
     // ---- aggressive early deflation -------------------------------------
     // Returns the number of deflated eigenvalues; fills the undeflated Ritz values.
     int aed(int ktop, int kbot, int nw, std::vector<Eig> &ritz, int *infqr = nullptr) {
-        double t0 = now_ms();
         nw = std::min(nw, kbot - ktop + 1);
-        nw = std::min(nw, nsmall_);
+        nw = std::min(nw, NEIG_AED_MAX);
+        if (nw > nsmall_) return aed_wide(ktop, kbot, nw, ritz, infqr);
+        double t0 = now_ms();
         const int kwtop = kbot - nw + 1;
         grow(&ws_.vt, &ws_.vt_cap, (size_t)nw * nw);
         grow(&ws_.dbuf, &ws_.dbuf_cap, (size_t)4 * nw + 64);
@@ -444,6 +487,94 @@ class Solver {
         stats_.aed_deflated += nd;
         stats_.small_flops += 10.0 * nw * (double)nw * nw;
         stats_.aed_flops += 10.0 * nw * (double)nw * nw;
+        stats_.alg_flops += 10.0 * nw * (double)nw * nw;
+        if (applied) stats_.alg_flops += 2.0 * nw * (double)nw * (kwtop + (n_ - kbot - 1) + n_);
+        stats_.t_aed_ms += now_ms() - t0;
+        return nd;
+    }
+
+    // AED on a window of more than nsmall_ rows (Section 3.2: the window's Schur
+    // form by a recursive application of the QR algorithm): the window is copied
+    // to the workspace and reduced by the whole method run on it (its own AED
+    // windows of at most nsmall_ rows, sweeps, small blocks), then k_aed_wide
+    // does the spike test, swaps and re-Hessenberg reduction there.
+    int aed_wide(int ktop, int kbot, int nw, std::vector<Eig> &ritz, int *infqr_out) {
+        double t0 = now_ms();
+        const int kwtop = kbot - nw + 1;
+        const int ld = nw;
+        const size_t nn = (size_t)nw * nw;
+        grow(&ws_.aw, &ws_.aw_cap, 3 * nn + 4 * (size_t)nw + 64);
+        grow_host(&ws_.h_dbuf, &ws_.h_dbuf_cap, (size_t)4 * nw + 64);
+        double *T = ws_.aw, *V = T + nn, *Vt = V + nn, *x = Vt + nn, *sr = x + nw, *si = sr + nw, *sp0 = si + nw;
+        const int gb = (int)std::min<size_t>((nn + 255) / 256, 1024);
+        timed(kOther, [&] {
+            hipLaunchKernelGGL(k_win_load, dim3(gb), dim3(256), 0, st_, H_, ldh_, kwtop, nw, T, ld, V, ld);
+            ck(hipGetLastError());
+        });
+        neig_params ip = p_;
+        ip.nw = p_.rec_nw > 0 ? std::min(p_.rec_nw, nsmall_) : 0;
+        ip.ns = p_.rec_ns;
+        ip.policy = 0;
+        ip.maxit = 0;
+        int inner_info = 0;
+        if (p_.timing) sync_collect();  // the inner solve reuses the event pool from its start
+        {
+            Solver in(nw, T, ld, V, ld, st_, ip);
+            inner_info = in.run();
+            if (inner_info < 0) throw HipFail{hipErrorInvalidValue};  // non-finite window
+            const neig_stats &q = in.stats_;
+            stats_.rec_inner_aeds += (double)q.aeds;
+            stats_.rec_inner_sweeps += (double)q.sweeps;
+            stats_.gemm_flops += q.gemm_flops;
+            stats_.chase_flops += q.chase_flops;
+            stats_.small_flops += q.small_flops;
+            stats_.aed_flops += q.aed_flops;  // the inner k_aed launches
+            stats_.gpu_update_ms += q.gpu_update_ms;
+            stats_.gpu_chase_ms += q.gpu_chase_ms;
+            stats_.gpu_aed_ms += q.gpu_aed_ms;
+            stats_.gpu_small_ms += q.gpu_small_ms;
+            stats_.gpu_other_ms += q.gpu_other_ms;
+            stats_.n_update += q.n_update;
+            stats_.n_chase += q.n_chase;
+            stats_.chase_bytes += q.chase_bytes;
+            stats_.aed_qr_iters += q.aed_qr_iters;
+            stats_.aed_swaps += q.aed_swaps;
+            stats_.aed_cyc_qr += q.aed_cyc_qr;
+            stats_.aed_cyc_defl += q.aed_cyc_defl;
+            stats_.aed_cyc_hess += q.aed_cyc_hess;
+            stats_.aed_late += q.aed_late;
+            stats_.swap_failures += q.swap_failures;
+        }
+        timed(kRecDefl, [&] {
+            hipLaunchKernelGGL(k_aed_wide, dim3(1), dim3(NT), 0, st_, H_, ldh_, ktop, kbot, T, V, ld, nw,
+                               inner_info, hnorm_, smlnum_, p_.deflation, x, ws_.ist, sr, si, sp0);
+            ck(hipGetLastError());
+        });
+        ck(hipMemcpyAsync(ws_.h_ist, ws_.ist, 12 * sizeof(int), hipMemcpyDeviceToHost, st_));
+        ck(hipMemcpyAsync(ws_.h_dbuf, sr, 2 * (size_t)nw * sizeof(double), hipMemcpyDeviceToHost, st_));
+        sync_collect();
+        const int nd = ws_.h_ist[0], nr = ws_.h_ist[1], applied = ws_.h_ist[2];
+        if (infqr_out) *infqr_out = ws_.h_ist[3];
+        if (ws_.h_ist[4]) stats_.swap_failures++;
+        stats_.aed_swaps += ws_.h_ist[6];
+        stats_.aed_cyc_defl += ws_.h_ist[8];
+        if (applied) stats_.aed_cyc_hess += ws_.h_ist[9];
+        stats_.aed_late += ws_.h_ist[10];
+        ritz.clear();
+        for (int t = 0; t < nr; ++t) ritz.push_back({ws_.h_dbuf[t], ws_.h_dbuf[nw + t]});
+        if (applied) {
+            timed(kOther, [&] {
+                hipLaunchKernelGGL(k_win_store, dim3(gb), dim3(256), 0, st_, H_, ldh_, ktop, kwtop, nw, T, V, ld,
+                                   Vt, ld, sp0);
+                ck(hipGetLastError());
+            });
+            std::vector<Task> tasks;
+            add_block_updates(tasks, kwtop, kbot, Vt, ld);
+            run_updates(tasks);
+        }
+        stats_.aeds++;
+        stats_.rec_aeds++;
+        stats_.aed_deflated += nd;
         stats_.alg_flops += 10.0 * nw * (double)nw * nw;
         if (applied) stats_.alg_flops += 2.0 * nw * (double)nw * (kwtop + (n_ - kbot - 1) + n_);
         stats_.t_aed_ms += now_ms() - t0;
@@ -512,6 +643,7 @@ class Solver {
                 const int mb = wn.r1 - b0 + 1, w = wn.r1 - wn.r0 + 1;
                 lds = std::max(lds, (size_t)(mb * (mb + 1) + w * (w + 1)) * sizeof(double));
                 stats_.chase_flops += 2.0 * 3 * nbs[c] * (double)(wn.t1 - wn.t0) * (2.0 * w + mb) * 2.0;
+                stats_.chase_bytes += 8.0 * (2.0 * mb * (double)mb + (double)w * w);
                 prev_r0 = wn.r0; prev_done = false; prev_ran = true;
                 ++idx[c];
             }
@@ -617,7 +749,7 @@ class Solver {
 
     int default_nw(int m) const {
         int nw = p_.nw > 0 ? p_.nw : (m < 300 ? 48 : 64);
-        nw = std::min(nw, nsmall_);
+        nw = std::min(nw, NEIG_AED_MAX);
         return std::min(nw, m);
     }
 
@@ -1229,7 +1361,7 @@ extern "C" int neig_aed(int n, double *H, int ldh, double *Z, int ldz, int ktop,
     std::lock_guard<std::mutex> lock(g_mutex);
     try {
         Solver s(n, H, ldh, Z, ldz, stream);
-        if (nw > s.nsmall()) return -8;
+        if (nw > NEIG_AED_MAX) return -8;
         if (!s.prep()) return -2;
         std::vector<Eig> ritz;
         *nd = s.aed(ktop, kbot, nw, ritz);
@@ -1570,6 +1702,9 @@ extern "C" int neig_set_params(const neig_params *p) {
     if (p->exc < 0) return -9;
     if (p->timing < 0 || p->timing > 1) return -10;
     if (p->policy < 0 || p->policy > 4) return -11;
+    if (p->nw > NEIG_AED_MAX) return -2;
+    if (p->rec_nw < 0 || p->rec_nw > NEIG_SMALL_MAX) return -13;
+    if (p->rec_ns < 0 || p->rec_ns % 2) return -14;
     std::lock_guard<std::mutex> lock(g_mutex);
     g_params = *p;
     return 0;

@@ -825,14 +825,15 @@ __device__ __forceinline__ bool aed_block_deflates(const double *T, const double
     return sp <= tol;
 }
 
-__device__ __forceinline__ AedOut aed_core(double *T, double *V, int ld, double *x, int nw, double s, double hnorm, double smlnum,
-                           int criterion, int maxit, double *sr, double *si) {
+// Second half of the AED step on a window already in real Schur form (rows
+// 0..o.infqr-1 unconverged and never tested): the spike test bottom-up with
+// block swaps, standardisation of the deflated 2x2 blocks, the undeflated Ritz
+// values, and the reduction of the spike and the undeflated part back to
+// Hessenberg form.  T, V and the vector scratch x (nw doubles) may be in LDS or
+// in global memory (generic pointers); all NT threads call.
+__device__ __forceinline__ void aed_deflate(double *T, double *V, int ld, double *x, int nw, double s, double hnorm,
+                                            double smlnum, int criterion, double *sr, double *si, AedOut &o) {
     const int tid = threadIdx.x;
-    AedOut o;
-    const long long c0 = clock64();
-    o.iters = 0;
-    o.infqr = lds_small_qr(T, ld, V, ld, nw, hnorm, smlnum, maxit, &o.iters);
-    __syncthreads();
     const long long c1 = clock64();
     o.nswap = 0;
     o.late = 0;
@@ -904,10 +905,9 @@ __device__ __forceinline__ AedOut aed_core(double *T, double *V, int ld, double 
     }
     o.nritz = c;
     o.spike0 = 0.0;
-    o.cyc_qr = c1 - c0;
     o.cyc_defl = c2 - c1;
     o.cyc_hess = 0;
-    if (o.nd == 0) return o;
+    if (o.nd == 0) return;
 
     if (kend > 0 && s != 0.0) {
         __syncthreads();
@@ -943,6 +943,17 @@ __device__ __forceinline__ AedOut aed_core(double *T, double *V, int ld, double 
     }
     __syncthreads();
     o.cyc_hess = clock64() - c2;
+}
+
+__device__ __forceinline__ AedOut aed_core(double *T, double *V, int ld, double *x, int nw, double s, double hnorm,
+                                           double smlnum, int criterion, int maxit, double *sr, double *si) {
+    AedOut o;
+    const long long c0 = clock64();
+    o.iters = 0;
+    o.infqr = lds_small_qr(T, ld, V, ld, nw, hnorm, smlnum, maxit, &o.iters);
+    __syncthreads();
+    o.cyc_qr = clock64() - c0;
+    aed_deflate(T, V, ld, x, nw, s, hnorm, smlnum, criterion, sr, si, o);
     return o;
 }
 
