@@ -1,0 +1,213 @@
+"""Autotuner for the single-matrix Schur reduction (``neig_schur``).
+
+The method's tunables (Section 3.2): the shifts per sweep ``ns``, the AED
+window ``nw`` (windows above 96 rows are solved recursively), the bulges per
+chain ``chain`` and the chase window ``chase_w``.  For each size bucket the
+tuner times ``neig_schur`` on that bucket's workload for candidate settings, by
+coordinate descent from the library's defaults, and keeps a candidate only if
+the solve converges and meets the backward-error and orthogonality bound
+50 n eps (checked with FP64 products on the GPU).  Buckets and workloads:
+
+* n <= 6000: the prescribed-spectrum workload at n = 4000 (2000 eigenvalues in
+  the unit disk, strictly upper part of T with standard deviation 0.1);
+* n > 6000: the random N(0,1) Hessenberg workload at n = 20000.
+
+The Hessenberg form of a dense uniform[-1,1] matrix (the paper's own kind of
+input) can be tuned as a third workload (``--hard N``); its optimum is
+recorded beside the table, not used by it.  The table is saved as JSON next to
+this file; :func:`apply` sets the parameters of the bucket an order falls in
+through ``neig_set_params``.
+
+Usage (on a GPU): ``python -m paper_2002_05024_amd.autotune_single``.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+SAVED = os.path.join(HERE, "tuned_single_gfx950.json")
+EPS = 2.0 ** -52
+
+GRID = {
+    "ns": [16, 32, 48, 64, 96, 128],
+    "nw": [48, 64, 80, 96, 128, 192],
+    "chain": [8, 12, 16],
+    "chase_w": [64, 80, 96],
+}
+DEFAULT = {"ns": 32, "nw": 64, "chain": 16, "chase_w": 96}
+
+
+def _valid(p) -> bool:
+    return p["chase_w"] >= 3 * p["chain"] + 2 and p["ns"] <= p["nw"]
+
+
+def workload(kind: str, n: int, dev):
+    """A device matrix (column-major) of the named workload."""
+    import numpy as np
+    import torch
+
+    from . import binding, inputs
+
+    if kind == "random":
+        g = inputs.rng(inputs.FULL, 0)
+        H = torch.from_numpy(g.standard_normal((n, n))).to(dev).t()  # row-major fill, column-major view
+        H.triu_(-1)
+    elif kind == "prescribed":
+        Hh, _ = inputs.prescribed_hessenberg(n, inputs.rng(inputs.PRESCRIBED, 4200), 0.1)
+        H = torch.from_numpy(np.ascontiguousarray(Hh.T)).to(dev).t()
+    elif kind == "hard":
+        g = inputs.rng(inputs.FULL, 31)
+        H = torch.from_numpy(g.uniform(-1.0, 1.0, (n, n))).to(dev).t()
+        binding.hessenberg(H)
+        H.triu_(-1)
+    else:
+        raise ValueError(kind)
+    torch.cuda.synchronize()
+    return H
+
+
+class Timer:
+    """Timed, checked neig_schur runs on one workload (H restored and Z reset
+    untimed before each run)."""
+
+    def __init__(self, H0):
+        import torch
+
+        self.H0 = H0
+        self.H = torch.empty_like(H0)
+        self.Z = torch.empty_like(H0)
+
+    def run(self, p, check=True):
+        import torch
+
+        from . import binding
+
+        binding.set_params(ns=p["ns"], nw=p["nw"], chain=p["chain"], chase_w=p["chase_w"])
+        self.H.copy_(self.H0)
+        self.Z.zero_()
+        self.Z.diagonal().fill_(1.0)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        r = binding.schur(self.H, self.Z)
+        e1.record()
+        torch.cuda.synchronize()
+        sec = e0.elapsed_time(e1) / 1000.0
+        if r.info != 0:
+            return None
+        if check:
+            n = self.H0.shape[0]
+            R = torch.mm(torch.mm(self.Z, self.H), self.Z.t())
+            R.sub_(self.H0)
+            be = float(torch.linalg.norm(R) / torch.linalg.norm(self.H0))
+            del R
+            E = torch.mm(self.Z.t(), self.Z)
+            E.diagonal().sub_(1.0)
+            oe = float(torch.linalg.norm(E))
+            del E
+            if not (be <= 50 * n * EPS and oe <= 50 * n * EPS):
+                return None
+        return sec
+
+
+def tune_workload(timer, passes: int = 2, log=print):
+    """Coordinate descent over GRID from DEFAULT; returns (best params, seconds,
+    default seconds, trials)."""
+    best = dict(DEFAULT)
+    t_def = timer.run(best)
+    best_t = t_def
+    trials = [(dict(best), t_def)]
+    log(f"  default {best} {t_def}")
+    for _ in range(passes):
+        improved = False
+        for key, vals in GRID.items():
+            for v in vals:
+                if v == best[key]:
+                    continue
+                cand = dict(best)
+                cand[key] = v
+                if not _valid(cand):
+                    continue
+                t = timer.run(cand)
+                trials.append((cand, t))
+                log(f"  {cand} {t}")
+                if t is not None and (best_t is None or t < best_t):
+                    best, best_t, improved = cand, t, True
+        if not improved:
+            break
+    return best, best_t, t_def, trials
+
+
+def tune(n_small: int = 4000, n_large: int = 20000, hard: int = 0, passes: int = 2, log=print):
+    import torch
+
+    from . import binding
+
+    dev = torch.device("cuda:0")
+    binding.load_library()
+    saved = binding.get_params()
+    out = {"buckets": [], "device": torch.cuda.get_device_name(0)}
+    try:
+        for n_hi, kind, n in ((6000, "prescribed", n_small), (None, "random", n_large)):
+            log(f"bucket n<={n_hi}: {kind} n={n}")
+            t0 = time.perf_counter()
+            timer = Timer(workload(kind, n, dev))
+            best, t, t_def, trials = tune_workload(timer, passes, log)
+            out["buckets"].append({"n_hi": n_hi, **best, "workload": f"{kind} n={n}", "seconds": t,
+                                   "default_seconds": t_def, "trials": len(trials),
+                                   "tuning_s": round(time.perf_counter() - t0, 1)})
+            del timer
+            torch.cuda.empty_cache()
+        if hard:
+            log(f"hard n={hard}")
+            timer = Timer(workload("hard", hard, dev))
+            best, t, t_def, trials = tune_workload(timer, passes, log)
+            out["hard_optimum"] = {**best, "workload": f"hard n={hard}", "seconds": t, "default_seconds": t_def}
+            del timer
+            torch.cuda.empty_cache()
+    finally:
+        binding.set_params(**saved)
+    return out
+
+
+def params_for(n: int, table) -> dict:
+    for b in table["buckets"]:
+        if b["n_hi"] is None or n <= b["n_hi"]:
+            return {k: b[k] for k in ("ns", "nw", "chain", "chase_w")}
+    return dict(DEFAULT)
+
+
+def apply(n: int, path: str = SAVED):
+    """Set the tuned parameters for order n through neig_set_params; returns
+    them, or None when there is no saved table."""
+    from . import binding
+
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        table = json.load(f)
+    p = params_for(n, table)
+    binding.set_params(**p)
+    return p
+
+
+def main():
+    ap = argparse.ArgumentParser(description="tune neig_schur's parameters per size bucket")
+    ap.add_argument("--out", default=SAVED)
+    ap.add_argument("--small", type=int, default=4000)
+    ap.add_argument("--large", type=int, default=20000)
+    ap.add_argument("--hard", type=int, default=0)
+    ap.add_argument("--passes", type=int, default=2)
+    a = ap.parse_args()
+    table = tune(a.small, a.large, a.hard, a.passes, log=lambda *x: print(*x, file=sys.stderr, flush=True))
+    with open(a.out, "w") as f:
+        json.dump(table, f, indent=1)
+    print(json.dumps(table), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -305,3 +305,194 @@ extern "C" __global__ void __launch_bounds__(UPW_THREADS) k_update_wide(UpdArgs 
         default: upw_body<24>(T, tile, lds); break;
     }
 }
+
+// ---------------------------------------------------------------- persistent update kernel
+//
+// k_update_p<NRT>: the update tasks for factors of order w <= 16 NRT <= 96 with
+// the factor held in registers.  The launch has a few workgroups per compute
+// unit; each loops over 64-wide slices of the tasks' strips (64 columns for
+// side 0, 64 rows for side 1).  Workgroup: NRT waves.  Wave q owns the 16-wide
+// tile q along w and all four 16-wide tiles across the slice; the part of the
+// factor it multiplies with (rows 16q.. of U^T for side 0, columns 16q.. of U
+// for side 1, all 4 NRT k-steps) is loaded into registers once per task.  Per
+// slice: the slice goes from registers into LDS, the next slice's elements
+// (16 per thread) are requested from HBM, the waves multiply from LDS while
+// they are in flight, and the results go from the accumulators straight to
+// HBM.  With one LDS buffer per workgroup several workgroups share a compute
+// unit, so one's barriers and loads overlap another's matrix-core work.
+#define UPDP_PER 16  // slice elements per thread
+#define UPDP_OOB 0x7ffffff8  // a buffer offset past every slice's range: loads give 0, stores are dropped
+
+typedef unsigned int updp_u2 __attribute__((ext_vector_type(2)));
+
+// Buffer resource over one slice of a strip (raw addressing, range-checked in
+// bytes): out-of-range elements of partial slices load as zero and their
+// stores are discarded, with no branches.  dword3 is the gfx9 family's
+// buffer format word.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t updp_rsrc(const UpdTask &T, int s, int *nvalid) {
+    const int base = s * UPD_SLICE;
+    const int nv = min(UPD_SLICE, T.len - base);  // columns (side 0) or rows (side 1) of the slice
+    *nvalid = nv;
+    double *p;
+    int bytes;
+    if (T.side == 0) {
+        p = T.C + (size_t)base * T.ldc;
+        bytes = ((nv - 1) * T.ldc + T.w) * 8;
+    } else {
+        p = T.C + base;
+        bytes = ((T.w - 1) * T.ldc + nv) * 8;
+    }
+    return __builtin_amdgcn_make_buffer_rsrc(p, (short)0, bytes, 0x00020000);
+}
+
+template <int NRT>
+__device__ __forceinline__ void updp_load(const UpdTask &T, int s, double (&pre)[UPDP_PER]) {
+    constexpr int wp = 16 * NRT;
+    int nv;
+    const __amdgpu_buffer_rsrc_t rs = updp_rsrc(T, s, &nv);
+    const int tid = threadIdx.x;
+    if (T.side == 0) {  // element e: row tid % wp, column tid / wp + 4 e (64 NRT threads = 4 wp)
+        const int r = tid % wp, c = tid / wp;
+#pragma unroll
+        for (int e = 0; e < UPDP_PER; ++e) {
+            const int off = (r < T.w && c + 4 * e < nv) ? (r + (c + 4 * e) * T.ldc) * 8 : UPDP_OOB;
+            pre[e] = __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(rs, off, 0, 0));
+        }
+    } else {  // element e: row tid % 64, column tid / 64 + NRT e
+        const int r = tid & 63, c = tid >> 6;
+#pragma unroll
+        for (int e = 0; e < UPDP_PER; ++e) {
+            const int off = (r < nv && c + NRT * e < T.w) ? (r + (c + NRT * e) * T.ldc) * 8 : UPDP_OOB;
+            pre[e] = __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(rs, off, 0, 0));
+        }
+    }
+}
+
+template <int NRT>
+__device__ __forceinline__ void updp_stage(int side, const double (&pre)[UPDP_PER], double *buf) {
+    constexpr int wp = 16 * NRT;
+    const int tid = threadIdx.x;
+    if (side == 0) {
+        const int r = tid % wp, c = tid / wp;
+#pragma unroll
+        for (int e = 0; e < UPDP_PER; ++e) buf[r + (c + 4 * e) * (wp + 1)] = pre[e];
+    } else {
+        const int r = tid & 63, c = tid >> 6;
+#pragma unroll
+        for (int e = 0; e < UPDP_PER; ++e) buf[r + (c + NRT * e) * (UPD_SLICE + 1)] = pre[e];
+    }
+}
+
+template <int NRT>
+__global__ void __launch_bounds__(64 * NRT) __attribute__((amdgpu_waves_per_eu(3))) k_update_p(UpdArgs args,
+                                                                                               int nslice) {
+    extern __shared__ double lds[];
+    constexpr int wp = 16 * NRT;
+    constexpr int NK = 4 * NRT;  // k-steps of 4
+    const int lane = threadIdx.x & 63;
+    const int q = threadIdx.x >> 6;  // tile along w
+    const int li = lane & 15, lk = lane >> 4;
+    int s = blockIdx.x;
+    if (s >= nslice) return;
+    int ti = 0;
+    while (ti + 1 < args.ntask && args.t[ti + 1].tile0 <= s) ++ti;
+    UpdTask T = args.t[ti];
+    double frag[NK];
+    auto load_frag = [&]() {
+        const int rw = 16 * q + li;
+#pragma unroll
+        for (int k = 0; k < NK; ++k) {
+            const int kk = 4 * k + lk;
+            frag[k] = (rw < T.w && kk < T.w) ? AT(T.Ut, T.ldu, rw, kk) : 0.0;
+        }
+        // complete these loads here, so that the slice loads issued later are
+        // never waited for by the products that use the factor
+        __builtin_amdgcn_s_waitcnt(0);
+    };
+    load_frag();
+    double pre[UPDP_PER];
+    updp_load<NRT>(T, s - T.tile0, pre);
+    for (;;) {
+        __syncthreads();  // every wave is done reading the buffer
+        updp_stage<NRT>(T.side, pre, lds);
+        __syncthreads();
+        const int sn = s + (int)gridDim.x;
+        const bool more = sn < nslice;
+        int tn = ti;
+        if (more) {
+            while (tn + 1 < args.ntask && args.t[tn + 1].tile0 <= sn) ++tn;
+            updp_load<NRT>(args.t[tn], sn - args.t[tn].tile0, pre);
+        }
+        neig_d4 acc[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[j] = (neig_d4){0.0, 0.0, 0.0, 0.0};
+        int nv;
+        const __amdgpu_buffer_rsrc_t rs = updp_rsrc(T, s - T.tile0, &nv);
+        if (T.side == 0) {
+            constexpr int ldb = wp + 1;
+            const double *bp = lds + li * ldb + lk;
+            // one k-step's operands read ahead of its products; the scheduling
+            // barriers keep the compiler from hoisting every LDS read up front
+            double b[4], bn[4];
+#pragma unroll
+            for (int j = 0; j < 4; ++j) b[j] = bp[16 * j * ldb];
+#pragma unroll
+            for (int k = 0; k < NK; ++k) {
+                if (k + 1 < NK) {
+#pragma unroll
+                    for (int j = 0; j < 4; ++j) bn[j] = bp[16 * j * ldb + 4 * (k + 1)];
+                }
+#pragma unroll
+                for (int j = 0; j < 4; ++j) acc[j] = mfma16(frag[k], b[j], acc[j]);
+#pragma unroll
+                for (int j = 0; j < 4; ++j) b[j] = bn[j];
+                __builtin_amdgcn_sched_barrier(0);
+            }
+            const int row0 = 16 * q + lk;
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int row = row0 + 4 * r, col = 16 * j + li;
+                    const int off = (row < T.w && col < nv) ? (row + col * T.ldc) * 8 : UPDP_OOB;
+                    const double v = acc[j][r];  // a scalar first: a vector element is not an object to bit-cast
+                    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(updp_u2, v), rs, off, 0, 0);
+                }
+        } else {
+            constexpr int lda = UPD_SLICE + 1;
+            const double *ap = lds + li + lk * lda;
+            double a[4], an[4];
+#pragma unroll
+            for (int j = 0; j < 4; ++j) a[j] = ap[16 * j];
+#pragma unroll
+            for (int k = 0; k < NK; ++k) {
+                if (k + 1 < NK) {
+#pragma unroll
+                    for (int j = 0; j < 4; ++j) an[j] = ap[16 * j + 4 * (k + 1) * lda];
+                }
+#pragma unroll
+                for (int j = 0; j < 4; ++j) acc[j] = mfma16(a[j], frag[k], acc[j]);
+#pragma unroll
+                for (int j = 0; j < 4; ++j) a[j] = an[j];
+                __builtin_amdgcn_sched_barrier(0);
+            }
+            const int col = 16 * q + li;
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int row = 16 * j + lk + 4 * r;
+                    const int off = (col < T.w && row < nv) ? (row + col * T.ldc) * 8 : UPDP_OOB;
+                    const double v = acc[j][r];  // a scalar first: a vector element is not an object to bit-cast
+                    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(updp_u2, v), rs, off, 0, 0);
+                }
+        }
+        if (!more) break;
+        if (tn != ti) {
+            ti = tn;
+            T = args.t[ti];
+            load_frag();
+        }
+        s = sn;
+    }
+}

@@ -223,6 +223,31 @@ double now_ms() {
     return duration<double, std::milli>(steady_clock::now().time_since_epoch()).count();
 }
 
+// Dynamic LDS of k_update_p<nrt>: one slice buffer.
+size_t update_p_lds(int nrt) {
+    const size_t wp = 16 * (size_t)nrt;
+    return std::max((wp + 1) * UPD_SLICE, (size_t)(UPD_SLICE + 1) * wp) * sizeof(double);
+}
+
+// Resident workgroups of k_update_p<NRT> per compute unit (queried once per device).
+template <int NRT>
+int update_p_occupancy(DeviceWs &ws) {
+    static int occ[kMaxDevices] = {0};
+    int dev = 0;
+    ck(hipGetDevice(&dev));
+    if (occ[dev] == 0) {
+        allow_dynamic_lds((const void *)k_update_p<NRT>, ws.lds_max);
+        int nb = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_update_p<NRT>, 64 * NRT, update_p_lds(NRT)) !=
+                hipSuccess ||
+            nb < 1)
+            nb = 1;
+        (void)hipGetLastError();
+        occ[dev] = nb;
+    }
+    return occ[dev];
+}
+
 // ----------------------------------------------------------------------------
 class Solver {
   public:
@@ -357,7 +382,6 @@ class Solver {
             UpdArgs a;
             std::memset(&a, 0, sizeof(a));
             int tiles = 0, nt = 0, wmaxp = 16;
-            bool any_left = false;
             for (; i < tasks.size() && nt < UPD_MAX_TASKS; ++i) {
                 const Task &t = tasks[i];
                 if (t.len <= 0 || t.w <= 0) continue;
@@ -366,18 +390,32 @@ class Solver {
                 u.tile0 = tiles;
                 tiles += (t.len + UPD_SLICE - 1) / UPD_SLICE;
                 wmaxp = std::max(wmaxp, (t.w + 15) & ~15);
-                if (t.side == 0) any_left = true;
                 stats_.gemm_flops += 2.0 * t.w * (double)t.w * t.len;
             }
             a.ntask = nt;
             if (nt == 0 || tiles == 0) continue;
-            size_t lds = (size_t)wmaxp * (wmaxp + 1) * sizeof(double);  // U^T
-            if (any_left) lds += (size_t)(wmaxp + 1) * UPD_SLICE * sizeof(double);
-            timed(kUpdate, [&] {
-                hipLaunchKernelGGL(k_update, dim3(tiles), dim3(UPD_THREADS), lds, st_, a);
-                ck(hipGetLastError());
-            });
+            launch_update_p(a, tiles, (wmaxp + 15) / 16);
         }
+    }
+
+    void launch_update_p(const UpdArgs &a, int nslice, int nrt) {
+        switch (nrt) {
+            case 1: launch_update_nrt<1>(a, nslice); break;
+            case 2: launch_update_nrt<2>(a, nslice); break;
+            case 3: launch_update_nrt<3>(a, nslice); break;
+            case 4: launch_update_nrt<4>(a, nslice); break;
+            case 5: launch_update_nrt<5>(a, nslice); break;
+            default: launch_update_nrt<6>(a, nslice); break;
+        }
+    }
+
+    template <int NRT>
+    void launch_update_nrt(const UpdArgs &a, int nslice) {
+        const int grid = std::min(nslice, ws_.cus * update_p_occupancy<NRT>(ws_));
+        timed(kUpdate, [&] {
+            hipLaunchKernelGGL(k_update_p<NRT>, dim3(grid), dim3(64 * NRT), update_p_lds(NRT), st_, a, nslice);
+            ck(hipGetLastError());
+        });
     }
 
     // tasks with factors of order UPD_WMAX+1 .. UPW_WMAX: U^T streamed from L2,
