@@ -291,8 +291,12 @@ def prescribed_leg(args, dev):
 
     from paper_2002_05024_amd import inputs
 
+    from paper_2002_05024_amd import autotune_single, binding
+
     n = args.prescribed
-    out = {}
+    saved = binding.get_params()
+    tuned = autotune_single.apply(n)
+    out = {"params": dict(tuned or {}, source="autotuned table" if tuned else "library defaults")}
     for tag, std, idx in (("as_written_std_0.1", 0.1, 4200), ("well_conditioned_std_0.1_over_sqrt_n",
                                                               0.1 / np.sqrt(n), 4201)):
         t0 = time.perf_counter()
@@ -315,6 +319,7 @@ def prescribed_leg(args, dev):
         out[tag] = rec
         del H0, S, Z
         torch.cuda.empty_cache()
+    binding.set_params(**saved)
     out["workload"] = (f"prescribed spectrum, n={n}: {n - 2 * (n // 4)} real eigenvalues and {n // 4} conjugate "
                        "pairs in the unit disk, Hessenberg form, Z from I")
     return out
@@ -342,30 +347,48 @@ def hard_leg(args, dev):
     A.triu_(-1)
     torch.cuda.synchronize()
     print(f"[bench] hard input n={n} ready in {time.perf_counter() - t0:.1f}s", file=sys.stderr, flush=True)
+    from paper_2002_05024_amd import autotune_single
+
     saved = binding.get_params()
-    binding.set_params(timing=int(args.timing))
+    table = autotune_single.load()
+    hp = None
+    if table and "hard_optimum" in table:
+        hp = {k: table["hard_optimum"][k] for k in ("ns", "nw", "chain", "chase_w")}
+        binding.set_params(**hp)
     H = A.clone(memory_format=torch.preserve_format)
     Z = torch.zeros_like(A)
-    Z.diagonal().fill_(1.0)
-    torch.cuda.synchronize()
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    e0.record()
-    r = binding.schur(H, Z)
-    e1.record()
-    torch.cuda.synchronize()
-    sec = e0.elapsed_time(e1) / 1000.0
-    st = binding.get_stats()
+
+    def solve(timing):
+        binding.set_params(timing=timing)
+        H.copy_(A)
+        Z.zero_()
+        Z.diagonal().fill_(1.0)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        r = binding.schur(H, Z)
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / 1000.0, r, binding.get_stats()
+
+    sec, r, st = solve(0)
+    print(f"[bench] hard n={n} {sec:.2f}s info={r.info}", file=sys.stderr, flush=True)
+    kst = None
+    if args.timing:  # a second reduction with HIP events around every launch, for the kernel figures
+        _, _, kst = solve(1)
     binding.set_params(**saved)
     out = {"workload": f"Hessenberg form (neig_hessenberg) of a dense uniform[-1,1] matrix, n={n}, Z from I",
            "seconds": round(sec, 3), "info": r.info,
+           "params": dict(hp, source="autotuned on another matrix of this kind (n=8000)") if hp else
+           {"source": "library defaults"},
            "gflops_algorithmic": round(st["alg_flops"] / sec / 1e9, 1),
            "gflops_update_executed": round(st["gemm_flops"] / sec / 1e9, 1),
            "counts": {"sweeps": st["sweeps"], "aeds": st["aeds"], "shifts": st["shifts_used"],
                       "aed_deflated": st["aed_deflated"]},
            "paper_context": "Table 3, n=20000: StarNEig 85 s on 28 Broadwell cores (one node), ScaLAPACK 158 s"}
-    if args.timing:
-        out.update(rooflines([st]))
-        out["gpu_ms"] = {k: round(st[f"gpu_{k}_ms"], 1) for k in ("update", "chase", "aed", "small", "other")}
+    if kst:
+        out.update(rooflines([kst]))
+        out["gpu_ms"] = {k: round(kst[f"gpu_{k}_ms"], 1) for k in ("update", "chase", "aed", "small", "other")}
     if args.check:
         be, oe = backward_and_orth(A, H, Z)
         out["check"] = {"backward_error": be, "orthogonality": oe, "bound_50n_eps": 50 * n * 2.0 ** -52}
@@ -603,7 +626,10 @@ def main():
     Z = torch.empty_like(H0)
     print(f"[bench] input n={n} ready in {time.perf_counter() - t_gen:.1f}s", file=sys.stderr, flush=True)
     saved = binding.get_params()
-    binding.set_params(timing=int(args.timing))
+    from paper_2002_05024_amd import autotune_single
+
+    tuned = autotune_single.apply(n)  # the tuned parameters of this order's bucket, when a table is saved
+    binding.set_params(timing=0)
 
     def restore():
         H.copy_(H0)
@@ -635,6 +661,17 @@ def main():
         print(f"[bench] step {k} {dt:.3f}s info={r.info}", file=sys.stderr, flush=True)
         if r.info != 0:
             raise SystemExit(f"step {k} did not converge: info={r.info}")
+    kstats = []
+    if args.timing:
+        # one more reduction, outside the timed steps, with HIP events around
+        # every launch: the per-kernel durations behind the roofline figures
+        # (the events add host work, so the timed steps run without them)
+        binding.set_params(timing=1)
+        restore()
+        r = binding.schur(H, Z)
+        torch.cuda.synchronize()
+        kstats.append(binding.get_stats())
+        binding.set_params(timing=0)
     binding.set_params(**saved)
 
     sec = sum(times) / len(times)
@@ -664,11 +701,14 @@ def main():
                    "shifts": st["shifts_used"], "exceptional": st["exceptional"],
                    "aed_qr_iters": st["aed_qr_iters"], "aed_swaps": st["aed_swaps"]},
         "aed_cycles_M": {k: round(st[f"aed_cyc_{k}"] / 1e6, 1) for k in ("qr", "defl", "hess")},
+        "params": dict(tuned or {}, source="autotuned table (paper_2002_05024_amd/tuned_single_gfx950.json)"
+                       if tuned else "library defaults"),
     }
-    if args.timing:
-        line.update(rooflines(stats))
-        line["gpu_ms_per_step"] = {k: round(sum(s[f"gpu_{k}_ms"] for s in stats) / len(stats), 1)
+    if kstats:
+        line.update(rooflines(kstats))
+        line["gpu_ms_per_step"] = {k: round(sum(s[f"gpu_{k}_ms"] for s in kstats) / len(kstats), 1)
                                    for k in ("update", "chase", "aed", "small", "other")}
+        line["gpu_ms_per_step"]["note"] = "one extra reduction with HIP events around every launch"
     if args.check:
         be, oe = backward_and_orth(H0, H, Z)
         line["check"] = {"backward_error": be, "orthogonality": oe, "bound_50n_eps": 50 * n * 2.0 ** -52}

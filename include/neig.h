@@ -70,7 +70,12 @@ typedef struct neig_params {
     int rec_nw;    /* deflation window used inside a recursively solved AED window
                       (nw > 96; at most 96); 0: the default rule for the window's order */
     int rec_ns;    /* shifts per sweep inside a recursively solved AED window            */
-    int reserved[2];
+    int aed_ends;  /* 0: aggressive early deflation on the trailing window and, while the
+                      active block is large and that end keeps deflating, on the leading
+                      window too (the same step on the flipped block J B^T J, which is
+                      upper Hessenberg again), both in one launch on two compute units;
+                      1: the trailing window only                                        */
+    int reserved[1];
 } neig_params;
 
 /* Largest AED window.  Windows of at most 96 rows are solved in one workgroup's
@@ -103,6 +108,8 @@ typedef struct neig_stats {
     double rec_aeds, rec_inner_aeds, rec_inner_sweeps, gpu_rec_defl_ms;
     double chase_bytes;  /* algorithmic bytes of the chase windows: 8 (2 mb^2 + w^2) per window
                             (its block of H loaded and stored, its factor stored)            */
+    double aeds_top, aed_top_deflated;  /* leading-window AED steps (counted in aeds too) and
+                                           the eigenvalues they deflated                    */
 } neig_stats;
 
 /*
@@ -224,7 +231,9 @@ int neig_sweep(int n, double *H, int ldh, double *Z, int ldz, int ktop, int kbot
  * Schur form of the window, spike test of every diagonal block from the bottom
  * up, failing blocks moved to the top of the window, the remaining spike
  * reduced by a Householder Hessenberg reduction, and the window's orthogonal
- * factor applied to the rest of H and to Z.
+ * factor applied to the rest of H and to Z.  Windows of at most 96 rows are
+ * solved in one workgroup's LDS; 97..NEIG_AED_MAX rows by the whole method run
+ * recursively on the window.
  *   nd           host out: number of deflated eigenvalues (rows kbot-nd+1..kbot
  *                are now decoupled and in Schur form).
  *   nshift       host out: number of undeflated Ritz values written to sr/si
@@ -233,6 +242,22 @@ int neig_sweep(int n, double *H, int ldh, double *Z, int ldz, int ktop, int kbot
  */
 int neig_aed(int n, double *H, int ldh, double *Z, int ldz, int ktop, int kbot, int nw, int *nd, int *nshift,
              double *sr, double *si, hipStream_t stream);
+
+/*
+ * neig_aed_top -- the same deflation step on the leading window of the active
+ * block: rows/cols ktop..ktop+nw-1, coupled to the rest of the block by
+ * H(ktop+nw, ktop+nw-1).  It is the AED step (Section 3.2) of the flipped
+ * block J B^T J (B = H(ktop:kbot, ktop:kbot), J the reversal), which is upper
+ * Hessenberg with the window at its bottom; mapped back, the deflated
+ * eigenvalues end in a leading quasi-triangular block rows/cols
+ * ktop..ktop+nd-1 with H(ktop+nd, ktop+nd-1) = 0.  neig_schur runs it beside
+ * the trailing-window step while the active block is large (neig_params
+ * aed_ends).  Arguments, updates of H and Z, results and error codes as
+ * neig_aed; nw <= 96.  The Ritz values returned are those of the leading
+ * window's undeflated part.
+ */
+int neig_aed_top(int n, double *H, int ldh, double *Z, int ldz, int ktop, int kbot, int nw, int *nd, int *nshift,
+                 double *sr, double *si, hipStream_t stream);
 
 /*
  * neig_small_schur -- real Schur form of a matrix small enough to live in one

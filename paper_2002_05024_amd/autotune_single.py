@@ -52,15 +52,16 @@ def workload(kind: str, n: int, dev):
 
     from . import binding, inputs
 
+    # seeds differ from the benchmark's inputs of the same kind
     if kind == "random":
-        g = inputs.rng(inputs.FULL, 0)
+        g = inputs.rng(inputs.FULL, 7)
         H = torch.from_numpy(g.standard_normal((n, n))).to(dev).t()  # row-major fill, column-major view
         H.triu_(-1)
     elif kind == "prescribed":
-        Hh, _ = inputs.prescribed_hessenberg(n, inputs.rng(inputs.PRESCRIBED, 4200), 0.1)
+        Hh, _ = inputs.prescribed_hessenberg(n, inputs.rng(inputs.PRESCRIBED, 4300), 0.1)
         H = torch.from_numpy(np.ascontiguousarray(Hh.T)).to(dev).t()
     elif kind == "hard":
-        g = inputs.rng(inputs.FULL, 31)
+        g = inputs.rng(inputs.FULL, 37)
         H = torch.from_numpy(g.uniform(-1.0, 1.0, (n, n))).to(dev).t()
         binding.hessenberg(H)
         H.triu_(-1)
@@ -174,6 +175,13 @@ def tune(n_small: int = 4000, n_large: int = 20000, hard: int = 0, passes: int =
     return out
 
 
+def load(path: str = SAVED):
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        return json.load(f)
+
+
 def params_for(n: int, table) -> dict:
     for b in table["buckets"]:
         if b["n_hi"] is None or n <= b["n_hi"]:
@@ -186,10 +194,9 @@ def apply(n: int, path: str = SAVED):
     them, or None when there is no saved table."""
     from . import binding
 
-    if not os.path.exists(path):
+    table = load(path)
+    if table is None:
         return None
-    with open(path) as f:
-        table = json.load(f)
     p = params_for(n, table)
     binding.set_params(**p)
     return p

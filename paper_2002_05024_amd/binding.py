@@ -43,7 +43,8 @@ class Params(ctypes.Structure):
         ("seed", _i),
         ("rec_nw", _i),
         ("rec_ns", _i),
-        ("reserved", _i * 2),
+        ("aed_ends", _i),
+        ("reserved", _i * 1),
     ]
 
 
@@ -86,6 +87,8 @@ class Stats(ctypes.Structure):
         ("rec_inner_sweeps", ctypes.c_double),
         ("gpu_rec_defl_ms", ctypes.c_double),
         ("chase_bytes", ctypes.c_double),
+        ("aeds_top", ctypes.c_double),
+        ("aed_top_deflated", ctypes.c_double),
     ]
 
 
@@ -136,6 +139,8 @@ def load_library():
     lib.neig_sweep.restype = _i
     lib.neig_aed.argtypes = [_i, _vp, _i, _vp, _i, _i, _i, _i, _ip, _ip, _dp, _dp, _vp]
     lib.neig_aed.restype = _i
+    lib.neig_aed_top.argtypes = [_i, _vp, _i, _vp, _i, _i, _i, _i, _ip, _ip, _dp, _dp, _vp]
+    lib.neig_aed_top.restype = _i
     lib.neig_small_schur.argtypes = [_i, _vp, _i, _vp, _i, _vp, _vp, _vp]
     lib.neig_small_schur.restype = _i
     lib.neig_set_params.argtypes = [ctypes.POINTER(Params)]
@@ -254,13 +259,15 @@ def sweep(H, Z, ktop, kbot, shifts_re, shifts_im, stream=None) -> int:
     return info
 
 
-def aed(H, Z, ktop, kbot, nw, stream=None):
-    """One aggressive-early-deflation step on the trailing window of [ktop, kbot].
-    Returns (nd, shifts_re, shifts_im): deflated count and the undeflated Ritz
-    values (shift candidates, bottom-most last)."""
+def aed(H, Z, ktop, kbot, nw, stream=None, leading=False):
+    """One aggressive-early-deflation step on the trailing window of [ktop, kbot]
+    (or, with ``leading``, on its leading window).  Returns (nd, shifts_re,
+    shifts_im): deflated count and the undeflated Ritz values (shift
+    candidates, bottom-most last)."""
     import numpy as np
 
     lib = load_library()
+    fn = lib.neig_aed_top if leading else lib.neig_aed
     n = H.shape[0]
     ldh = _check_matrix("H", H, n)
     ldz = _check_matrix("Z", Z, n)
@@ -268,10 +275,10 @@ def aed(H, Z, ktop, kbot, nw, stream=None):
     nsh = ctypes.c_int(0)
     sr = np.zeros(max(nw, 1))
     si = np.zeros(max(nw, 1))
-    info = lib.neig_aed(n, ctypes.c_void_p(H.data_ptr()), ldh, ctypes.c_void_p(Z.data_ptr()), ldz,
-                        int(ktop), int(kbot), int(nw), ctypes.byref(nd), ctypes.byref(nsh),
-                        sr.ctypes.data_as(_dp), si.ctypes.data_as(_dp), _stream_ptr(stream))
-    _raise("neig_aed", info)
+    info = fn(n, ctypes.c_void_p(H.data_ptr()), ldh, ctypes.c_void_p(Z.data_ptr()), ldz, int(ktop), int(kbot),
+              int(nw), ctypes.byref(nd), ctypes.byref(nsh), sr.ctypes.data_as(_dp), si.ctypes.data_as(_dp),
+              _stream_ptr(stream))
+    _raise("neig_aed_top" if leading else "neig_aed", info)
     k = nsh.value
     return nd.value, sr[:k].copy(), si[:k].copy()
 

@@ -30,6 +30,7 @@
 #include <cmath>
 #include <complex>
 #include <cstring>
+#include <map>
 #include <mutex>
 #include <vector>
 
@@ -490,45 +491,95 @@ class Solver {
         nw = std::min(nw, kbot - ktop + 1);
         nw = std::min(nw, NEIG_AED_MAX);
         if (nw > nsmall_) return aed_wide(ktop, kbot, nw, ritz, infqr);
+        std::vector<Eig> unused;
+        AedEnd r = aed_ends(ktop, kbot, nw, 0, ritz, unused);
+        if (infqr) *infqr = r.infqr;
+        return r.nd;
+    }
+
+    // AED at the two ends of the active block [ktop, kbot] in one k_aed launch
+    // (one workgroup per window): the trailing window of nw_bot rows (Section
+    // 3.2) and, when nw_top > 0, the leading window of nw_top rows, handled as
+    // the trailing window of the flipped block.  Either size may be 0 (that end
+    // is skipped); both at most nsmall_, and the two windows must not overlap.
+    // The windows' factors are applied to the rest of H and to Z; the leading
+    // window's row strip overlaps the trailing window's column strip, so those
+    // go in separate update launches.  Returns the trailing window's result;
+    // the leading window's deflation count goes to *nd_top.
+    struct AedEnd {
+        int nd, infqr;
+    };
+
+    AedEnd aed_ends(int ktop, int kbot, int nw_bot, int nw_top, std::vector<Eig> &ritz_bot,
+                    std::vector<Eig> &ritz_top, int *nd_top = nullptr) {
         double t0 = now_ms();
-        const int kwtop = kbot - nw + 1;
-        grow(&ws_.vt, &ws_.vt_cap, (size_t)nw * nw);
-        grow(&ws_.dbuf, &ws_.dbuf_cap, (size_t)4 * nw + 64);
-        grow_host(&ws_.h_dbuf, &ws_.h_dbuf_cap, (size_t)4 * nw + 64);
-        const size_t lds = (size_t)(2 * nw * (nw + 1) + nw) * sizeof(double);
-        const int maxit = 30 * std::max(10, nw);
+        const int nwm = std::max(nw_bot, nw_top);
+        grow(&ws_.vt, &ws_.vt_cap, (size_t)2 * nwm * nwm);
+        grow(&ws_.dbuf, &ws_.dbuf_cap, (size_t)4 * nwm + 64);
+        grow_host(&ws_.h_dbuf, &ws_.h_dbuf_cap, (size_t)4 * nwm + 64);
+        AedJobs jobs;
+        std::memset(&jobs, 0, sizeof(jobs));
+        // job j: factor at vt + j nwm^2, status at ist + 16 j, Ritz values at dbuf + 2 nwm j
+        int nj = 0, jb = -1;
+        auto add_job = [&](int nw, int flip) {
+            const int j = nj++;
+            jobs.j[j] = {ktop, kbot, nw, flip, ws_.vt + (size_t)j * nwm * nwm, ws_.ist + 16 * j,
+                         ws_.dbuf + (size_t)2 * nwm * j, ws_.dbuf + (size_t)2 * nwm * j + nwm};
+            return j;
+        };
+        if (nw_bot > 0) jb = add_job(nw_bot, 0);
+        if (nw_top > 0) add_job(nw_top, 1);
+        AedEnd res{0, 0};
+        if (nd_top) *nd_top = 0;
+        if (nj == 0) return res;
+        const size_t lds = (size_t)(2 * nwm * (nwm + 1) + nwm) * sizeof(double);
+        const int maxit = 30 * std::max(10, nwm);
         timed(kAed, [&] {
-            hipLaunchKernelGGL(k_aed, dim3(1), dim3(NT), lds, st_, H_, ldh_, ktop, kbot, nw, hnorm_, smlnum_,
-                               p_.deflation, maxit, ws_.vt, nw, ws_.ist, ws_.dbuf, ws_.dbuf + nw);
+            hipLaunchKernelGGL(k_aed, dim3(nj), dim3(NT), lds, st_, H_, ldh_, jobs, hnorm_, smlnum_, p_.deflation,
+                               maxit, nwm);
             ck(hipGetLastError());
         });
-        ck(hipMemcpyAsync(ws_.h_ist, ws_.ist, 12 * sizeof(int), hipMemcpyDeviceToHost, st_));
-        ck(hipMemcpyAsync(ws_.h_dbuf, ws_.dbuf, 2 * nw * sizeof(double), hipMemcpyDeviceToHost, st_));
+        ck(hipMemcpyAsync(ws_.h_ist, ws_.ist, 28 * sizeof(int), hipMemcpyDeviceToHost, st_));
+        ck(hipMemcpyAsync(ws_.h_dbuf, ws_.dbuf, 4 * (size_t)nwm * sizeof(double), hipMemcpyDeviceToHost, st_));
         sync_collect();
-        const int nd = ws_.h_ist[0], nr = ws_.h_ist[1], applied = ws_.h_ist[2];
-        if (infqr) *infqr = ws_.h_ist[3];
-        if (ws_.h_ist[4]) stats_.swap_failures++;
-        stats_.aed_qr_iters += ws_.h_ist[5];
-        stats_.aed_swaps += ws_.h_ist[6];
-        stats_.aed_cyc_qr += ws_.h_ist[7];
-        stats_.aed_cyc_defl += ws_.h_ist[8];
-        if (applied) stats_.aed_cyc_hess += ws_.h_ist[9];
-        stats_.aed_late += ws_.h_ist[10];
-        ritz.clear();
-        for (int t = 0; t < nr; ++t) ritz.push_back({ws_.h_dbuf[t], ws_.h_dbuf[nw + t]});
-        if (applied) {
-            std::vector<Task> tasks;
-            add_block_updates(tasks, kwtop, kbot, ws_.vt, nw);
-            run_updates(tasks);
+        for (int j = 0; j < nj; ++j) {
+            const int *st = ws_.h_ist + 16 * j;
+            const AedJob &J = jobs.j[j];
+            const int nw = J.nw, nd = st[0], nr = st[1], applied = st[2];
+            if (st[4]) stats_.swap_failures++;
+            stats_.aed_qr_iters += st[5];
+            stats_.aed_swaps += st[6];
+            stats_.aed_cyc_qr += st[7];
+            stats_.aed_cyc_defl += st[8];
+            if (applied) stats_.aed_cyc_hess += st[9];
+            stats_.aed_late += st[10];
+            std::vector<Eig> &ritz = (j == jb) ? ritz_bot : ritz_top;
+            const double *hsr = ws_.h_dbuf + (size_t)2 * nwm * j;
+            ritz.clear();
+            for (int t = 0; t < nr; ++t) ritz.push_back({hsr[t], hsr[nwm + t]});
+            if (j == jb) {
+                res.nd = nd;
+                res.infqr = st[3];
+            } else {
+                if (nd_top) *nd_top = nd;
+                stats_.aeds_top += 1;
+                stats_.aed_top_deflated += nd;
+            }
+            stats_.aeds++;
+            stats_.aed_deflated += nd;
+            stats_.small_flops += 10.0 * nw * (double)nw * nw;
+            stats_.aed_flops += 10.0 * nw * (double)nw * nw;
+            stats_.alg_flops += 10.0 * nw * (double)nw * nw;
+            if (applied) {
+                const int lo = J.flip ? ktop : kbot - nw + 1, hi = lo + nw - 1;
+                std::vector<Task> tasks;
+                add_block_updates(tasks, lo, hi, J.Vt, nwm);
+                run_updates(tasks);  // one launch per window (see above)
+                stats_.alg_flops += 2.0 * nw * (double)nw * (lo + (n_ - hi - 1) + n_);
+            }
         }
-        stats_.aeds++;
-        stats_.aed_deflated += nd;
-        stats_.small_flops += 10.0 * nw * (double)nw * nw;
-        stats_.aed_flops += 10.0 * nw * (double)nw * nw;
-        stats_.alg_flops += 10.0 * nw * (double)nw * nw;
-        if (applied) stats_.alg_flops += 2.0 * nw * (double)nw * (kwtop + (n_ - kbot - 1) + n_);
         stats_.t_aed_ms += now_ms() - t0;
-        return nd;
+        return res;
     }
 
     // AED on a window of more than nsmall_ rows (Section 3.2: the window's Schur
@@ -874,8 +925,15 @@ class Solver {
         PolicySample pending;
         bool have_pending = false;
         double t_decide = 0.0;
+        std::map<int, int> done;  // rows [first, last] deflated at the top of an active block, by last
+        int top_fail = 0;         // leading-window AEDs in a row that deflated nothing
         while (kbot >= 0) {
-            const int ktop = scan(kbot);
+            const auto dn = done.find(kbot);
+            if (dn != done.end()) {  // already in Schur form: skip to the rows above
+                kbot = dn->second - 1;
+                continue;
+            }
+            int ktop = scan(kbot);
             const int m = kbot - ktop + 1;
             if (m <= nmin_) {
                 int bad = small_block(ktop, kbot);
@@ -884,6 +942,7 @@ class Solver {
                     break;
                 }
                 kbot = ktop - 1;
+                top_fail = 0;
                 ndefl = 0;
                 have_pending = false;
                 nw_next = ns_next = 0;
@@ -895,7 +954,31 @@ class Solver {
             }
             stats_.iterations++;
             const int nw = nw_next > 0 ? std::min(nw_next, m) : default_nw(m);
-            const int nd = aed(ktop, kbot, nw, ritz);
+            int nd = 0;
+            if (nw <= nsmall_) {
+                // the leading window too while the block is large enough for two
+                // disjoint windows and that end keeps deflating
+                const int nw_top = (p_.aed_ends == 0 && top_fail < 3 && m >= 2 * nw + 32) ? nw : 0;
+                int nd_top = 0;
+                std::vector<Eig> ritz_top;
+                nd = aed_ends(ktop, kbot, nw, nw_top, ritz, ritz_top, &nd_top).nd;
+                if (nd_top > 0) {
+                    const int last = ktop + nd_top - 1;
+                    int first = ktop;
+                    const auto prev = done.find(ktop - 1);  // extend the range deflated just above
+                    if (prev != done.end()) {
+                        first = prev->second;
+                        done.erase(prev);
+                    }
+                    done[last] = first;
+                    ktop += nd_top;
+                    top_fail = 0;
+                } else if (nw_top > 0) {
+                    ++top_fail;
+                }
+            } else {
+                nd = aed(ktop, kbot, nw, ritz);
+            }
             if (have_pending) {  // reward of the last proposal: this window's deflations per ms
                 pending.nd = (float)nd;
                 pending.ms = (float)(now_ms() - t_decide);
@@ -1469,6 +1552,39 @@ void launch_batched_pair(int batch, const int *n, double *const *H, const int *l
 }
 
 }  // namespace
+
+extern "C" int neig_aed_top(int n, double *H, int ldh, double *Z, int ldz, int ktop, int kbot, int nw, int *nd,
+                            int *nshift, double *sr, double *si, hipStream_t stream) {
+    int a = check_args(n, H, ldh, Z, ldz);
+    if (a) return a;
+    if (ktop < 0 || ktop >= n) return -6;
+    if (kbot < ktop || kbot >= n) return -7;
+    if (nw < 1 || nw > kbot - ktop + 1) return -8;
+    if (!nd) return -9;
+    if (!nshift) return -10;
+    if (!sr) return -11;
+    if (!si) return -12;
+    std::lock_guard<std::mutex> lock(g_mutex);
+    try {
+        Solver s(n, H, ldh, Z, ldz, stream);
+        if (nw > s.nsmall()) return -8;
+        if (!s.prep()) return -2;
+        std::vector<Eig> unused, ritz;
+        int ndt = 0;
+        s.aed_ends(ktop, kbot, 0, nw, unused, ritz, &ndt);
+        *nd = ndt;
+        *nshift = (int)ritz.size();
+        for (size_t i = 0; i < ritz.size(); ++i) {
+            sr[i] = ritz[i].re;
+            si[i] = ritz[i].im;
+        }
+        s.sync();
+        g_stats = s.stats_;
+        return 0;
+    } catch (const HipFail &f) {
+        return -100 - (int)f.e;
+    }
+}
 
 extern "C" int neig_schur_batched(int batch, const int *n, double *const *H, const int *ldh, double *const *Z,
                                   const int *ldz, double *const *wr, double *const *wi, int *info,

@@ -957,6 +957,25 @@ __device__ __forceinline__ AedOut aed_core(double *T, double *V, int ld, double 
     return o;
 }
 
+// One AED window of a k_aed launch.  flip = 0: the trailing window of the
+// active block [ktop, kbot] (rows/cols kbot-nw+1..kbot, coupled to the rest by
+// H(kwtop, kwtop-1)).  flip = 1: the leading window (rows/cols ktop..ktop+nw-1,
+// coupled by H(ktop+nw, ktop+nw-1)), handled as the trailing window of the
+// flipped block J B^T J (B the active block, J the reversal), which is upper
+// Hessenberg again: the window is loaded as J W^T J, the same AED runs on it,
+// and the result is mapped back (T -> J T^T J, V -> J V J), so its deflated
+// eigenvalues end at the top of the window.
+struct AedJob {
+    int ktop, kbot, nw, flip;
+    double *Vt;   // V^T out (ld ldvt)
+    int *status;  // 12 ints (layout below)
+    double *sr, *si;
+};
+
+struct AedJobs {
+    AedJob j[2];
+};
+
 // status: [0] nd (deflated count), [1] number of Ritz values written to sr/si,
 // [2] 1 if H and the window transform V were updated (the host then applies V^T
 // to the rest of H and Z), [3] rows not converged by the window QR, [4] 1 if a
@@ -965,18 +984,33 @@ __device__ __forceinline__ AedOut aed_core(double *T, double *V, int ld, double 
 // re-Hessenberg reduction with the write-back, [10] deflations found above a
 // block that failed the test.
 extern "C" __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(1, 1)))
-k_aed(double *H, int ldh, int ktop, int kbot, int nw, double hnorm, double smlnum, int criterion, int maxit,
-      double *Vt, int ldvt, int *status, double *sr, double *si) {
+k_aed(double *H, int ldh, AedJobs jobs, double hnorm, double smlnum, int criterion, int maxit, int ldvt) {
     extern __shared__ double lds[];
+    const AedJob J = jobs.j[blockIdx.x];
+    const int nw = J.nw;
     const int ld = nw + 1;
     double *T = lds;
     double *V = lds + (size_t)nw * ld;
     double *x = V + (size_t)nw * ld;  // nw doubles of vector scratch
-    const int kwtop = kbot - nw + 1;
-    const double s = (kwtop > ktop) ? AT(H, ldh, kwtop, kwtop - 1) : 0.0;
-    lds_load_block(H, ldh, kwtop, nw, T, ld, V, ld);
-    const AedOut o = aed_core(T, V, ld, x, nw, s, hnorm, smlnum, criterion, maxit, sr, si);
+    int off;
+    double s;
+    if (!J.flip) {
+        off = J.kbot - nw + 1;
+        s = (off > J.ktop) ? AT(H, ldh, off, off - 1) : 0.0;
+        lds_load_block(H, ldh, off, nw, T, ld, V, ld);
+    } else {
+        off = J.ktop;
+        s = (off + nw <= J.kbot) ? AT(H, ldh, off + nw, off + nw - 1) : 0.0;
+        for (int idx = threadIdx.x; idx < nw * nw; idx += NT) {
+            const int i = idx % nw, j = idx / nw;
+            AT(T, ld, i, j) = (i <= j + 1) ? AT(H, ldh, off + nw - 1 - j, off + nw - 1 - i) : 0.0;
+            AT(V, ld, i, j) = (i == j) ? 1.0 : 0.0;
+        }
+        __syncthreads();
+    }
+    const AedOut o = aed_core(T, V, ld, x, nw, s, hnorm, smlnum, criterion, maxit, J.sr, J.si);
     if (threadIdx.x == 0) {
+        int *status = J.status;
         status[0] = o.nd;
         status[1] = o.nritz;
         status[2] = (o.nd > 0) ? 1 : 0;
@@ -990,8 +1024,17 @@ k_aed(double *H, int ldh, int ktop, int kbot, int nw, double hnorm, double smlnu
         status[10] = o.late;
     }
     if (o.nd == 0) return;  // H untouched; only the shifts are used
-    lds_store(H, ldh, kwtop, nw, T, ld, V, ld, Vt, ldvt);
-    if (kwtop > ktop && threadIdx.x == 0) AT(H, ldh, kwtop, kwtop - 1) = o.spike0;
+    if (!J.flip) {
+        lds_store(H, ldh, off, nw, T, ld, V, ld, J.Vt, ldvt);
+        if (off > J.ktop && threadIdx.x == 0) AT(H, ldh, off, off - 1) = o.spike0;
+    } else {
+        for (int idx = threadIdx.x; idx < nw * nw; idx += NT) {
+            const int r = idx % nw, c = idx / nw;
+            AT(H, ldh, off + r, off + c) = (r <= c + 1) ? AT(T, ld, nw - 1 - c, nw - 1 - r) : 0.0;
+            AT(J.Vt, ldvt, r, c) = AT(V, ld, nw - 1 - c, nw - 1 - r);
+        }
+        if (off + nw <= J.kbot && threadIdx.x == 0) AT(H, ldh, off + nw, off + nw - 1) = o.spike0;
+    }
 }
 
 // ---------------------------------------------------------------- reordering window

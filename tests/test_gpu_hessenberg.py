@@ -70,6 +70,29 @@ def test_hessenberg_ragged_large_matches_oracle(neig):
     assert dh <= 10.0 and dq <= 50.0
 
 
+def test_hessenberg_wide_chunk_path(neig):
+    """n = 8704: trailing blocks of more than 8192 rows take the wide-chunk
+    matrix-vector path (the one the n = 20000 benchmark runs); checked by
+    backward error, orthogonality and exact zeros, with FP64 products on the
+    GPU (the oracle would take minutes here)."""
+    import torch
+
+    n = 8704
+    g = inputs.rng(95, n)
+    A0 = torch.from_numpy(g.standard_normal((n, n))).cuda().t()  # column-major view
+    A = A0.clone(memory_format=torch.preserve_format)
+    Q = torch.eye(n, dtype=torch.float64, device="cuda").t()
+    say(f"hessenberg n={n} (wide chunks)")
+    neig.hessenberg(A, Q)
+    torch.cuda.synchronize()
+    assert float(torch.tril(A, -2).abs().max()) == 0.0
+    # A0 = Q H Q^T: the backward error of the similarity with S := H
+    be = gpu_backward_error(A0, A, Q)
+    oe = gpu_orthogonality(Q)
+    say(f"  backward {be:.2e} orth {oe:.2e}")
+    assert be <= 50 * n * EPS and oe <= 50 * n * EPS
+
+
 @pytest.mark.parametrize("n", [0, 1, 2])
 def test_hessenberg_trivial_sizes(neig, n):
     A = inputs.rng(96, n).standard_normal((n, n))

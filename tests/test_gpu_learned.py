@@ -4,8 +4,8 @@ spectrum, row-graded Hessenberg), with the backward-error check judging every
 result.  The network's weights are the committed file written by the
 training stage of ``paper_2002_05024_amd.learn``; it is used as that module's
 evaluation uses it (one proposal per matrix, ``policy = 4``).  The gain is
-printed per matrix and in total; the full held-out evaluation (200 matrices)
-is run by ``learn evaluate``."""
+printed per matrix and in total, and the total must show a gain; the full
+held-out evaluation (200 matrices) is run by ``learn evaluate``."""
 import os
 
 import numpy as np
@@ -48,4 +48,7 @@ def test_learned_vs_default_on_heldout(neig):
         # every result that is kept meets the bound (the default rules re-solve a failure)
         assert r["be_net"] <= 50 * r["n"] * eps and r["oe_net"] <= 50 * r["n"] * eps
         assert r["be_default"] <= 50 * r["n"] * eps
-    assert np.isfinite(summary["speedup"])
+    # the committed network measured 1.07x over all 200 held-out matrices and
+    # about 1.2x on these small ones (each arm timed first on every other
+    # matrix, after an untimed warm-up); the test asks for a gain of at least 2%
+    assert summary["speedup"] > 1.02, summary["speedup"]

@@ -114,6 +114,8 @@ def oracle_sweep(H, shifts, ilo, ihi):
     (60, 4, 50, 3, 0, 0),       # interior block: full-width updates outside it
     (150, 0, 149, 6, 2, 16),    # three chains, many small windows
     (200, 0, 199, 8, 4, 40),    # two chains, windows with overlap
+    (600, 0, 599, 24, 16, 96),  # the default shape: a full 16-bulge chain and a second one, 96-row windows
+    (700, 10, 650, 32, 16, 96),  # two full chains chased concurrently on an interior block
 ])
 def test_sweep_implicit_q(neig, n, ktop, kbot, nbul, chain, chase_w):
     say(f"sweep n={n} [{ktop},{kbot}] bulges={nbul} chain={chain} w={chase_w}")
