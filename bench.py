@@ -136,7 +136,7 @@ def cpu_baseline(samples, n_target):
     }
 
 
-KERNEL_SOURCES = {"k_aed": "small.hip", "k_small_qr": "small.hip", "k_update": "gemm.hip", "k_chase": "chase.hip"}
+KERNEL_SOURCES = {"k_aed": "small.hip", "k_small_qr": "small.hip", "k_update_p": "gemm.hip", "k_chase": "chase.hip"}
 
 
 def kernel_source_sha(kernel):
@@ -174,9 +174,9 @@ def rooflines(stats):
     form), k_update 2 w^2 len flops per task, k_chase the bytes of its windows
     (load and store of the window of H, store of U)."""
     aed_ms = sum(s["gpu_aed_ms"] for s in stats)
-    # k_aed launches: AED windows solved in LDS, including those inside the
+    # k_aed launches (one or two windows each), including those inside the
     # recursive solves of wide windows
-    aed_n = sum(s["aeds"] - s["rec_aeds"] + s["rec_inner_aeds"] for s in stats)
+    aed_n = sum(s["aed_launches"] for s in stats)
     aed_fl = sum(s["aed_flops"] for s in stats)
     upd_ms = sum(s["gpu_update_ms"] for s in stats)
     upd_n = sum(s["n_update"] for s in stats)
@@ -196,9 +196,9 @@ def rooflines(stats):
     if upd_ms > 0:
         ach = upd_fl / (upd_ms / 1000.0) / 1e12
         out["roofline_update"] = {
-            "kernel": "k_update", "bound": "mfma", "achieved": round(ach, 3), "peak": FP64_MFMA_PEAK_TFLOPS,
+            "kernel": "k_update_p", "bound": "mfma", "achieved": round(ach, 3), "peak": FP64_MFMA_PEAK_TFLOPS,
             "unit": "TFLOP/s", "frac": round(ach / FP64_MFMA_PEAK_TFLOPS, 4),
-            "traffic": traffic_per_launch("k_update"),
+            "traffic": traffic_per_launch("k_update_p"),
             "avg_launch_us": round(upd_ms * 1000.0 / max(upd_n, 1), 2),
             "flops_per_launch": round(upd_fl / max(upd_n, 1), 1),
         }

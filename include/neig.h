@@ -110,6 +110,7 @@ typedef struct neig_stats {
                             (its block of H loaded and stored, its factor stored)            */
     double aeds_top, aed_top_deflated;  /* leading-window AED steps (counted in aeds too) and
                                            the eigenvalues they deflated                    */
+    double aed_launches;  /* launches of the LDS AED kernel (one or two windows each)      */
 } neig_stats;
 
 /*

@@ -89,6 +89,7 @@ class Stats(ctypes.Structure):
         ("chase_bytes", ctypes.c_double),
         ("aeds_top", ctypes.c_double),
         ("aed_top_deflated", ctypes.c_double),
+        ("aed_launches", ctypes.c_double),
     ]
 
 

@@ -534,6 +534,7 @@ class Solver {
         if (nj == 0) return res;
         const size_t lds = (size_t)(2 * nwm * (nwm + 1) + nwm) * sizeof(double);
         const int maxit = 30 * std::max(10, nwm);
+        stats_.aed_launches += 1;
         timed(kAed, [&] {
             hipLaunchKernelGGL(k_aed, dim3(nj), dim3(NT), lds, st_, H_, ldh_, jobs, hnorm_, smlnum_, p_.deflation,
                                maxit, nwm);
@@ -618,6 +619,7 @@ class Solver {
             stats_.chase_flops += q.chase_flops;
             stats_.small_flops += q.small_flops;
             stats_.aed_flops += q.aed_flops;  // the inner k_aed launches
+            stats_.aed_launches += q.aed_launches;
             stats_.gpu_update_ms += q.gpu_update_ms;
             stats_.gpu_chase_ms += q.gpu_chase_ms;
             stats_.gpu_aed_ms += q.gpu_aed_ms;
