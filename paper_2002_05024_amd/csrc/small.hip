@@ -498,6 +498,171 @@ __device__ __forceinline__ bool solve_cp(double (&M)[K][K], double (&r)[K], doub
     return ok;
 }
 
+// The swap transform from a solution X of the Sylvester equation A X - X C = B12
+// (A the leading P x P block of B, C the trailing Q x Q block, X(i, j) at index
+// i + P j): the columns of [[-X][I]] span C's invariant subspace, Qm is the
+// orthogonal factor of their QR factorisation and Bn = Qm^T B Qm.  Returns false
+// when Bn's lower-left block or the reconstruction error B - Qm Bn Qm^T is not at
+// roundoff level (then the swap is rejected).
+template <int P, int Q>
+__device__ __forceinline__ bool swap_from_x(const double (&B)[P + Q][P + Q], const double (&X)[P * Q], double bnorm,
+                                            double (&Qm)[P + Q][P + Q], double (&Bn)[P + Q][P + Q]) {
+    constexpr int N = P + Q;
+    constexpr int K = P * Q;
+#pragma unroll
+    for (int i = 0; i < N; ++i)
+#pragma unroll
+        for (int j = 0; j < N; ++j) Qm[i][j] = (i == j) ? 1.0 : 0.0;
+    double xm = 0.0;
+#pragma unroll
+    for (int t = 0; t < K; ++t) xm = fmax(xm, fabs(X[t]));
+    const double g = 1.0 / fmax(1.0, xm);
+    double Y[N][Q];
+#pragma unroll
+    for (int j = 0; j < Q; ++j)
+#pragma unroll
+        for (int i = 0; i < N; ++i) Y[i][j] = (i < P) ? -g * X[i + P * j] : ((i - P == j) ? g : 0.0);
+    // Householder QR of Y, reflectors accumulated into Qm
+#pragma unroll
+    for (int c = 0; c < Q; ++c) {
+        double v[N];
+#pragma unroll
+        for (int t = 0; t < N; ++t) v[t] = (t >= c) ? Y[t][c] : 0.0;
+        double mx = 0.0;
+#pragma unroll
+        for (int t = c + 1; t < N; ++t) mx = fmax(mx, fabs(v[t]));
+        if (mx == 0.0) continue;
+        const double sc = fmax(mx, fabs(v[c]));
+        const double rsc = 1.0 / sc;
+        double ss = 0.0;
+#pragma unroll
+        for (int t = c; t < N; ++t) ss += (v[t] * rsc) * (v[t] * rsc);
+        const double nrm = sc * sqrt(ss);
+        const double alpha = v[c];
+        const double beta = alpha >= 0.0 ? -nrm : nrm;
+        const double dd = alpha - beta;
+        const double qq = 1.0 / (beta * dd);  // one division for 1/beta and 1/(alpha - beta)
+        const double tau = -dd * dd * qq;     // (beta - alpha) / beta
+        const double inv = beta * qq;         // 1 / (alpha - beta)
+#pragma unroll
+        for (int t = c + 1; t < N; ++t) v[t] *= inv;
+        v[c] = 1.0;
+#pragma unroll
+        for (int j = c; j < Q; ++j) {
+            double d = 0.0;
+#pragma unroll
+            for (int t = c; t < N; ++t) d += v[t] * Y[t][j];
+            d *= tau;
+#pragma unroll
+            for (int t = c; t < N; ++t) Y[t][j] -= d * v[t];
+        }
+#pragma unroll
+        for (int i = 0; i < N; ++i) {
+            double d = 0.0;
+#pragma unroll
+            for (int t = c; t < N; ++t) d += Qm[i][t] * v[t];
+            d *= tau;
+#pragma unroll
+            for (int t = c; t < N; ++t) Qm[i][t] -= d * v[t];
+        }
+    }
+    // Bn = Qm^T (B Qm); B is block upper triangular (rows P.. are zero in
+    // columns ..P-1)
+    double W[N][N];
+#pragma unroll
+    for (int i = 0; i < N; ++i)
+#pragma unroll
+        for (int j = 0; j < N; ++j) {
+            double d = 0.0;
+#pragma unroll
+            for (int k = (i < P ? 0 : P); k < N; ++k) d += B[i][k] * Qm[k][j];
+            W[i][j] = d;
+        }
+#pragma unroll
+    for (int i = 0; i < N; ++i)
+#pragma unroll
+        for (int j = 0; j < N; ++j) {
+            double d = 0.0;
+#pragma unroll
+            for (int k = 0; k < N; ++k) d += Qm[k][i] * W[k][j];
+            Bn[i][j] = d;
+        }
+    const double thresh = fmax(20.0 * NEIG_EPS * bnorm, NEIG_DBL_MIN);
+    double low = 0.0;
+#pragma unroll
+    for (int j = 0; j < Q; ++j)
+#pragma unroll
+        for (int i = Q; i < N; ++i) {
+            low = fmax(low, fabs(Bn[i][j]));
+            Bn[i][j] = 0.0;
+        }
+    if (!(low <= thresh)) return false;
+    // reconstruction: B ~ Qm Bn Qm^T (Bn now block upper triangular: rows Q..
+    // are zero in columns ..Q-1)
+#pragma unroll
+    for (int i = 0; i < N; ++i)
+#pragma unroll
+        for (int j = 0; j < N; ++j) {
+            double d = 0.0;
+#pragma unroll
+            for (int k = (i < Q ? 0 : Q); k < N; ++k) d += Bn[i][k] * Qm[j][k];
+            W[i][j] = d;
+        }
+    double err = 0.0;
+#pragma unroll
+    for (int i = 0; i < N; ++i)
+#pragma unroll
+        for (int j = 0; j < N; ++j) {
+            double d = 0.0;
+#pragma unroll
+            for (int k = 0; k < N; ++k) d += Qm[i][k] * W[k][j];
+            err = fmax(err, fabs(d - B[i][j]));
+        }
+    return err <= thresh;
+}
+
+// Closed-form solve of the 2 x 2 Sylvester equation A X - X C = R.  With
+// p(z) = z^2 - tr(C) z + det(C) the characteristic polynomial of C,
+// Cayley-Hamilton (C^2 = tr(C) C - det(C) I) turns the equation into
+// p(A) X = A R + R (C - tr(C) I), a 2 x 2 linear system solved by its adjugate;
+// one step of residual correction follows.  Returns false when p(A) is singular
+// or the result is not finite (the caller then solves the 4 x 4 system).
+__device__ __forceinline__ bool sylv22_closed(const double (&B)[4][4], double (&X)[4]) {
+    const double a00 = B[0][0], a01 = B[0][1], a10 = B[1][0], a11 = B[1][1];
+    const double c00 = B[2][2], c01 = B[2][3], c10 = B[3][2], c11 = B[3][3];
+    const double trc = c00 + c11, detc = c00 * c11 - c01 * c10;
+    const double d = a00 + a11 - trc;
+    const double p00 = a00 * a00 + a01 * a10 - trc * a00 + detc;
+    const double p01 = a01 * d, p10 = a10 * d;
+    const double p11 = a10 * a01 + a11 * a11 - trc * a11 + detc;
+    const double detp = p00 * p11 - p01 * p10;
+    if (!(fabs(detp) > 0.0)) return false;
+    const double rd = 1.0 / detp;
+    const double q00 = p11 * rd, q01 = -p01 * rd, q10 = -p10 * rd, q11 = p00 * rd;  // p(A)^-1
+    // C - tr(C) I = [[-c11, c01], [c10, -c00]]
+    double r00 = B[0][2], r01 = B[0][3], r10 = B[1][2], r11 = B[1][3];
+    double x00 = 0.0, x01 = 0.0, x10 = 0.0, x11 = 0.0;
+#pragma unroll
+    for (int pass = 0; pass < 2; ++pass) {
+        const double s00 = a00 * r00 + a01 * r10 - r00 * c11 + r01 * c10;
+        const double s01 = a00 * r01 + a01 * r11 + r00 * c01 - r01 * c00;
+        const double s10 = a10 * r00 + a11 * r10 - r10 * c11 + r11 * c10;
+        const double s11 = a10 * r01 + a11 * r11 + r10 * c01 - r11 * c00;
+        x00 += q00 * s00 + q01 * s10;
+        x01 += q00 * s01 + q01 * s11;
+        x10 += q10 * s00 + q11 * s10;
+        x11 += q10 * s01 + q11 * s11;
+        if (pass == 0) {  // residual R - (A X - X C)
+            r00 = B[0][2] - (a00 * x00 + a01 * x10 - x00 * c00 - x01 * c10);
+            r01 = B[0][3] - (a00 * x01 + a01 * x11 - x00 * c01 - x01 * c11);
+            r10 = B[1][2] - (a10 * x00 + a11 * x10 - x10 * c00 - x11 * c10);
+            r11 = B[1][3] - (a10 * x01 + a11 * x11 - x10 * c01 - x11 * c11);
+        }
+    }
+    X[0] = x00; X[1] = x10; X[2] = x01; X[3] = x11;
+    return isfinite(x00) && isfinite(x01) && isfinite(x10) && isfinite(x11);
+}
+
 // Orthogonal Qm (N x N) and the swapped block Bn = Qm^T B Qm for block sizes (P, Q).
 template <int P, int Q>
 __device__ __forceinline__ bool swap_transform(const double (&B)[P + Q][P + Q], double (&Qm)[P + Q][P + Q],
@@ -509,13 +674,10 @@ __device__ __forceinline__ bool swap_transform(const double (&B)[P + Q][P + Q], 
 #pragma unroll
         for (int j = 0; j < N; ++j) bnorm = fmax(bnorm, fabs(B[i][j]));
     bnorm *= N;  // >= Frobenius norm
-#pragma unroll
-    for (int i = 0; i < N; ++i)
-#pragma unroll
-        for (int j = 0; j < N; ++j) Qm[i][j] = (i == j) ? 1.0 : 0.0;
     if constexpr (P == 1 && Q == 1) {
         const double a = B[0][0], b = B[0][1], c = B[1][1];
         const double x0 = b, x1 = c - a;
+        Qm[0][0] = 1.0; Qm[0][1] = 0.0; Qm[1][0] = 0.0; Qm[1][1] = 1.0;
         if (x0 == 0.0 && x1 == 0.0) {
 #pragma unroll
             for (int i = 0; i < N; ++i)
@@ -529,6 +691,11 @@ __device__ __forceinline__ bool swap_transform(const double (&B)[P + Q][P + Q], 
         Bn[0][0] = c; Bn[0][1] = b; Bn[1][0] = 0.0; Bn[1][1] = a;
         return true;
     } else {
+        if constexpr (P == 2 && Q == 2) {
+            double Xc[4];
+            if (sylv22_closed(B, Xc) && swap_from_x<2, 2>(B, Xc, bnorm, Qm, Bn)) return true;
+            PROF_CNT(7, 1);  // the closed form was rejected: 4 x 4 solve
+        }
         constexpr int K = P * Q;
         double M[K][K], rhs[K], X[K];
 #pragma unroll
@@ -548,112 +715,7 @@ __device__ __forceinline__ bool swap_transform(const double (&B)[P + Q][P + Q], 
                 for (int k = 0; k < Q; ++k) M[row][i + P * k] -= B[P + k][P + j];
             }
         if (!solve_cp<K>(M, rhs, X)) return false;
-        double xm = 0.0;
-#pragma unroll
-        for (int t = 0; t < K; ++t) xm = fmax(xm, fabs(X[t]));
-        const double g = 1.0 / fmax(1.0, xm);
-        double Y[N][Q];
-#pragma unroll
-        for (int j = 0; j < Q; ++j)
-#pragma unroll
-            for (int i = 0; i < N; ++i) Y[i][j] = (i < P) ? -g * X[i + P * j] : ((i - P == j) ? g : 0.0);
-        // Householder QR of Y, reflectors accumulated into Qm
-#pragma unroll
-        for (int c = 0; c < Q; ++c) {
-            double v[N];
-#pragma unroll
-            for (int t = 0; t < N; ++t) v[t] = (t >= c) ? Y[t][c] : 0.0;
-            double mx = 0.0;
-#pragma unroll
-            for (int t = c + 1; t < N; ++t) mx = fmax(mx, fabs(v[t]));
-            if (mx == 0.0) continue;
-            const double sc = fmax(mx, fabs(v[c]));
-            const double rsc = 1.0 / sc;
-            double ss = 0.0;
-#pragma unroll
-            for (int t = c; t < N; ++t) ss += (v[t] * rsc) * (v[t] * rsc);
-            const double nrm = sc * sqrt(ss);
-            const double alpha = v[c];
-            const double beta = alpha >= 0.0 ? -nrm : nrm;
-            const double dd = alpha - beta;
-            const double qq = 1.0 / (beta * dd);  // one division for 1/beta and 1/(alpha - beta)
-            const double tau = -dd * dd * qq;     // (beta - alpha) / beta
-            const double inv = beta * qq;         // 1 / (alpha - beta)
-#pragma unroll
-            for (int t = c + 1; t < N; ++t) v[t] *= inv;
-            v[c] = 1.0;
-#pragma unroll
-            for (int j = c; j < Q; ++j) {
-                double d = 0.0;
-#pragma unroll
-                for (int t = c; t < N; ++t) d += v[t] * Y[t][j];
-                d *= tau;
-#pragma unroll
-                for (int t = c; t < N; ++t) Y[t][j] -= d * v[t];
-            }
-#pragma unroll
-            for (int i = 0; i < N; ++i) {
-                double d = 0.0;
-#pragma unroll
-                for (int t = c; t < N; ++t) d += Qm[i][t] * v[t];
-                d *= tau;
-#pragma unroll
-                for (int t = c; t < N; ++t) Qm[i][t] -= d * v[t];
-            }
-        }
-        // Bn = Qm^T (B Qm); B is block upper triangular (rows P.. are zero in
-        // columns ..P-1)
-        double W[N][N];
-#pragma unroll
-        for (int i = 0; i < N; ++i)
-#pragma unroll
-            for (int j = 0; j < N; ++j) {
-                double d = 0.0;
-#pragma unroll
-                for (int k = (i < P ? 0 : P); k < N; ++k) d += B[i][k] * Qm[k][j];
-                W[i][j] = d;
-            }
-#pragma unroll
-        for (int i = 0; i < N; ++i)
-#pragma unroll
-            for (int j = 0; j < N; ++j) {
-                double d = 0.0;
-#pragma unroll
-                for (int k = 0; k < N; ++k) d += Qm[k][i] * W[k][j];
-                Bn[i][j] = d;
-            }
-        const double thresh = fmax(20.0 * NEIG_EPS * bnorm, NEIG_DBL_MIN);
-        double low = 0.0;
-#pragma unroll
-        for (int j = 0; j < Q; ++j)
-#pragma unroll
-            for (int i = Q; i < N; ++i) {
-                low = fmax(low, fabs(Bn[i][j]));
-                Bn[i][j] = 0.0;
-            }
-        if (!(low <= thresh)) return false;
-        // reconstruction: B ~ Qm Bn Qm^T (Bn now block upper triangular: rows Q..
-        // are zero in columns ..Q-1)
-#pragma unroll
-        for (int i = 0; i < N; ++i)
-#pragma unroll
-            for (int j = 0; j < N; ++j) {
-                double d = 0.0;
-#pragma unroll
-                for (int k = (i < Q ? 0 : Q); k < N; ++k) d += Bn[i][k] * Qm[j][k];
-                W[i][j] = d;
-            }
-        double err = 0.0;
-#pragma unroll
-        for (int i = 0; i < N; ++i)
-#pragma unroll
-            for (int j = 0; j < N; ++j) {
-                double d = 0.0;
-#pragma unroll
-                for (int k = 0; k < N; ++k) d += Qm[i][k] * W[k][j];
-                err = fmax(err, fabs(d - B[i][j]));
-            }
-        return err <= thresh;
+        return swap_from_x<P, Q>(B, X, bnorm, Qm, Bn);
     }
 }
 
