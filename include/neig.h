@@ -348,7 +348,8 @@ const char *neig_version(void);
  */
 #define NEIG_MLP_NPARAM 6848
 
-/* Bins of the two heads: ns_bins[8] shift counts, nw_bins[8] window sizes (host out). */
+/* Bins of the two heads: ns_bins[8] shift counts (8, 16, 24, 32, 48, 64, 96, 128),
+ * nw_bins[8] window sizes (32, 40, 48, 56, 64, 72, 80, 96) (host out). */
 int neig_policy_bins(int *ns_bins, int *nw_bins);
 
 /*

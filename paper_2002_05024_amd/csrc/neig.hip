@@ -61,8 +61,8 @@ std::mutex g_mutex;
 // Parameter-proposal network: bins of the two proposals, the weights (host copy,
 // uploaded to each device on first use after a change), the confidence below
 // which the default heuristics are used, and the log of the last run.
-const int kNsBins[MLP_NBIN] = {4, 8, 12, 16, 20, 24, 28, 32};
-const int kNwBins[MLP_NBIN] = {24, 32, 40, 48, 56, 64, 80, 96};
+const int kNsBins[MLP_NBIN] = {8, 16, 24, 32, 48, 64, 96, 128};
+const int kNwBins[MLP_NBIN] = {32, 40, 48, 56, 64, 72, 80, 96};
 struct PolicyState {
     std::vector<float> theta;  // empty: no network installed
     long long version = 0;

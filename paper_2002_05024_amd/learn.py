@@ -11,6 +11,9 @@ Stages, each run on a GPU:
                  n uniform in [1000, 8000]) is solved with the default rules and
                  with one (shift, window) bin pair held for the whole solve
                  (``policy = 3``); both solves' decisions and times are stored.
+``compact``      keeps the first decision of every solve of ``collect-run``
+                 files (all that ``train --smooth-k`` reads): the committed
+                 training set ``learn_runs_gfx950.npz``.
 ``train``        fits the network by weighted cross-entropy with the library's
                  own GPU kernels (``neig_mlp_grad`` + ``neig_mlp_adam``); for
                  per-run data a solve weighs exp(beta log(t_default / t_solve))
@@ -148,18 +151,28 @@ def collect(start: int, count: int, out: str, lo: int, hi: int, seed: int, threa
     _save(out, feats, bins, stats, runs)
 
 
+# The network's bins (the library's neig_policy_bins): shifts per sweep and
+# AED window rows.
+NS_BINS = (8, 16, 24, 32, 48, 64, 96, 128)
+NW_BINS = (32, 40, 48, 56, 64, 72, 80, 96)
+
+
+def bins_of(ns: int, nw: int):
+    return NS_BINS.index(ns), NW_BINS.index(nw)
+
+
 # Arms of the per-run exploration: (shift bin, window bin) pairs held for a
-# whole solve.  Shift bins 3, 5, 7 = 16, 24, 32 shifts; window bins 3, 5, 6, 7
-# = 48, 64, 80, 96 rows (the default rules use 32 shifts and a 64-row window
-# for active blocks of 300 rows or more).
-ARMS = [(a, b) for a in (3, 5, 7) for b in (3, 5, 6, 7)]
-# the arms that the first round of exploration found competitive somewhere
-FOCUSED_ARMS = [(7, 3), (5, 3), (5, 5), (7, 6)]
+# whole solve: 16, 32, 64 or 96 shifts with 48-, 64- or 80-row windows, less
+# the default rules' own pair (32 shifts and a 64-row window for active blocks
+# of 300 rows or more; 16 and 48 below).
+ARMS = [bins_of(a, b) for a in (16, 32, 64, 96) for b in (48, 64, 80) if (a, b) != (32, 64)]
+# arms for a focused round of exploration
+FOCUSED_ARMS = [bins_of(64, 64), bins_of(96, 64), bins_of(64, 80), bins_of(16, 48)]
 
 
 def default_bins(m):
     """The bins of the default rules for an active block of order m."""
-    return (7, 5) if m >= 300 else (3, 3)
+    return bins_of(32, 64) if m >= 300 else bins_of(16, 48)
 
 
 def collect_runs(start: int, count: int, out: str, lo: int, hi: int, threads: int, arms=None):
@@ -200,6 +213,20 @@ def collect_runs(start: int, count: int, out: str, lo: int, hi: int, threads: in
             _save_runs(out, rec)
     binding.set_params(policy=0, seed=0)
     _save_runs(out, rec)
+
+
+def compact_runs(files, out: str):
+    """The first decision of every solve of per-run files, in one file with the
+    same fields (default and arm solve of a matrix share its run id)."""
+    parts = [np.load(f) for f in files]
+    rec = {k: np.concatenate([p[k] for p in parts]) for k in parts[0].files}
+    key = rec["run"].astype(np.int64) * 64 + (rec["arm"] + 1)
+    _, first = np.unique(key, return_index=True)
+    first = np.sort(first)
+    tmp = out + ".tmp.npz"
+    np.savez_compressed(tmp, **{k: v[first] for k, v in rec.items()})
+    os.replace(tmp, out)
+    return len(first)
 
 
 def _save_runs(out, rec):
@@ -261,7 +288,7 @@ def smoothed_targets(X, arms, adv, k: int = 25, beta: float = 8.0):
         by = {}
         for j in nb:
             by.setdefault(int(arms[j]), []).append(adv[j])
-        choices = [((7, 5), 0.0)] + [(ARMS[a], float(np.mean(v))) for a, v in sorted(by.items())]
+        choices = [(default_bins(1000), 0.0)] + [(ARMS[a], float(np.mean(v))) for a, v in sorted(by.items())]
         w = np.exp(beta * np.array([v for _, v in choices]))
         w /= w.sum()
         out.append([(b, float(p)) for (b, _), p in zip(choices, w)])
@@ -462,6 +489,9 @@ def main():
     cr.add_argument("--count", type=int, default=100)
     cr.add_argument("--out", required=True)
     cr.add_argument("--focused", action="store_true", help="explore only FOCUSED_ARMS")
+    cp = sub.add_parser("compact")
+    cp.add_argument("data", nargs="+")
+    cp.add_argument("--out", required=True)
     t = sub.add_parser("train")
     t.add_argument("data", nargs="+")
     t.add_argument("--out", default=SAVED)
@@ -488,6 +518,8 @@ def main():
     elif args.cmd == "collect-run":
         collect_runs(args.start, args.count, args.out, args.lo, args.hi, args.threads,
                      FOCUSED_ARMS if args.focused else None)
+    elif args.cmd == "compact":
+        print(compact_runs(args.data, args.out), flush=True)
     elif args.cmd == "train":
         train(args.data, args.out, args.epochs, batch=args.batch, beta=args.beta, first_only=args.first_only,
               smooth_k=args.smooth_k)

@@ -1,6 +1,8 @@
 """Host-side logic that needs no GPU: the input generators of the batched and
 learned workloads, the training-weight rule, and the autotuner's candidate
 filter."""
+import os
+
 import numpy as np
 import pytest
 
@@ -78,6 +80,15 @@ def test_autotune_candidate_filter():
     assert not autotune._valid({"nw": 64, "ns": 32, "nmin": 96, "chase_w": 49})
 
 
+def test_network_bins_match_the_library():
+    from paper_2002_05024_amd import binding, learn
+
+    if not os.path.exists(binding.library_path()):
+        pytest.skip("libneig.so not built")
+    ns, nw = binding.policy_bins()
+    assert tuple(ns) == learn.NS_BINS and tuple(nw) == learn.NW_BINS
+
+
 def test_run_weights_rule():
     from paper_2002_05024_amd import learn
 
@@ -90,7 +101,8 @@ def test_run_weights_rule():
     # twice as fast: twice as much; twice as slow: half
     assert w[0] == pytest.approx(1.0) and w[3] == pytest.approx(1.0 / k)
     assert w[1] == pytest.approx(2.0) and w[2] == pytest.approx(0.5)
-    assert len(set(learn.ARMS)) == k and learn.default_bins(5000) == (7, 5) and learn.default_bins(200) == (3, 3)
+    assert len(set(learn.ARMS)) == k and learn.default_bins(5000) == (3, 4) and learn.default_bins(200) == (1, 2)
+    assert learn.default_bins(5000) not in learn.ARMS
 
 
 def test_run_weights_spread_over_decisions():
@@ -113,22 +125,51 @@ def test_smoothed_targets_follow_the_neighbourhood():
     from paper_2002_05024_amd import learn
 
     g = np.random.default_rng(0)
-    # two well separated groups of matrices; arm (7, 3) is faster in group A,
-    # slower in group B; the other arm tried is neutral
+    # two well separated groups of matrices; arm F (64 shifts, 48 rows) is
+    # faster in group A, slower in group B; the other arm tried is neutral
     XA = g.normal(0.0, 0.1, (20, 24))
     XB = g.normal(5.0, 0.1, (20, 24))
     X = np.vstack([XA, XB])
-    a73, a55 = learn.ARMS.index((7, 3)), learn.ARMS.index((5, 5))
-    arms = np.array([a73, a55] * 20)
-    adv = np.where(np.arange(40) < 20, np.where(arms == a73, 0.3, 0.0), np.where(arms == a73, -0.5, 0.0))
+    F, N = learn.bins_of(64, 48), learn.bins_of(16, 64)
+    aF, aN = learn.ARMS.index(F), learn.ARMS.index(N)
+    arms = np.array([aF, aN] * 20)
+    adv = np.where(np.arange(40) < 20, np.where(arms == aF, 0.3, 0.0), np.where(arms == aF, -0.5, 0.0))
     T = learn.smoothed_targets(X, arms, adv, k=10, beta=8.0)
+    default = learn.default_bins(1000)
     for i in range(40):
         probs = dict(T[i])
         assert abs(sum(probs.values()) - 1.0) < 1e-12
         best = max(probs, key=probs.get)
-        assert best == ((7, 3) if i < 20 else (7, 5)) or (i >= 20 and best == (5, 5))
+        assert best == (F if i < 20 else default) or (i >= 20 and best == N)
     ids, Xm, am, av = learn.per_matrix_rows(np.array([0, 0, 0, 1, 1]), np.array([-1, -1, 4, -1, 2]),
                                             np.array([2.0] * 5), np.array([2.0, 2.0, 1.0, 2.0, 4.0]),
                                             np.arange(5, dtype=float)[:, None] * np.ones((1, 3)))
     assert list(ids) == [0, 1] and list(am) == [4, 2]
     assert np.allclose(av, [np.log(2.0), np.log(0.5)]) and np.allclose(Xm[:, 0], [0.0, 3.0])
+
+
+def test_compact_runs_keeps_first_decisions(tmp_path):
+    from paper_2002_05024_amd import learn
+
+    # two files of per-run data: matrix 0 (default solve: 2 decisions, arm solve: 3)
+    # and matrix 1 (1 + 2); the compact file holds the first decision of each solve
+    def part(run, arm, feat0):
+        n = len(run)
+        return {"feat": np.arange(n, dtype=np.float32)[:, None] + feat0 + np.zeros((1, 24), np.float32),
+                "bins": np.zeros((n, 2), np.int32), "stats": np.zeros((n, 4), np.float32),
+                "run": np.array(run, np.int32), "t_def": np.full(n, 2.0, np.float32),
+                "t_run": np.array([2.0 if a < 0 else 1.0 for a in arm], np.float32),
+                "arm": np.array(arm, np.int32), "p_arm": np.full(n, 0.1, np.float32)}
+    a = part([0, 0, 0, 0, 0], [-1, -1, 3, 3, 3], 0.0)
+    b = part([1, 1, 1], [-1, 5, 5], 100.0)
+    fa, fb, out = tmp_path / "a.npz", tmp_path / "b.npz", str(tmp_path / "c.npz")
+    np.savez(fa, **a)
+    np.savez(fb, **b)
+    assert learn.compact_runs([str(fa), str(fb)], out) == 4
+    c = np.load(out)
+    assert list(c["run"]) == [0, 0, 1, 1] and list(c["arm"]) == [-1, 3, -1, 5]
+    assert list(c["feat"][:, 0]) == [0.0, 2.0, 100.0, 101.0]
+    full = {k: np.concatenate([a[k], b[k]]) for k in a}
+    r1 = learn.per_matrix_rows(full["run"], full["arm"], full["t_def"], full["t_run"], full["feat"])
+    r2 = learn.per_matrix_rows(c["run"], c["arm"], c["t_def"], c["t_run"], c["feat"])
+    assert all(np.array_equal(x, y) for x, y in zip(r1, r2))
