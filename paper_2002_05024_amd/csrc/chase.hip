@@ -205,8 +205,12 @@ k_chase(double *H, int ldh, const double *poly, double *Ut, ChaseArgs a) {
                 if (task < na * uc) {
                     k = task / uc;
                     row0 = (task - k * uc) * 64;
-                    nrow = w;
                     pc = ptop - 3 * k - r0;
+                    // U starts as I and each bulge passing a row moves its first
+                    // nonzero column left by at most 2, so rows below pc + 2 + 2 nb
+                    // are still zero in columns pc..pc+2: nothing to do there
+                    nrow = min(w, pc + 3 + 2 * nb);
+                    if (row0 >= nrow) continue;
                     M = Us; ldm = ldus;
                 } else {
                     const int h = task - na * uc;

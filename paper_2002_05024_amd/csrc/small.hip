@@ -260,42 +260,73 @@ __device__ __forceinline__ void near_steps(double *T, int ldt, int l, int i, int
     if (k < k1) near_step<2>(T, ldt, l, i, k, k0, cnear, rt, r1, r2, x0, x1, x2);
 }
 
+// The far-field update of a sweep's last batch of reflectors (columns right of
+// its near field, the rows above it, all of Q) may be left pending: every entry
+// it writes is strictly above the diagonal, so the deflation scan does not read
+// them, and the next sweep's waves 1-3 apply it while wave 0 chases the first
+// batch, when that batch's near field lies left of its columns.  Otherwise (and
+// before a 2x2 standardisation, shift inputs it may touch, or the end) it is
+// applied by all threads at once.
+struct FarPending {
+    int k0, nb, cnear, buf;  // the batch (k0 < 0: none) and its reflector buffer
+};
+
+__device__ __forceinline__ void far_flush(double *T, int ldt, double *Q, int ldq, int m, FarPending &pf,
+                                          double (*rq)[3][FB]) {
+    if (pf.k0 < 0) return;
+    PROF_T(pf0);
+    far_apply(T, ldt, Q, ldq, m, pf.k0, pf.nb, pf.cnear + 1, m - 1, pf.k0, true, rq[pf.buf][0], rq[pf.buf][1],
+              rq[pf.buf][2], threadIdx.x, NT);
+    __syncthreads();
+    PROF_ADD(2, pf0);
+    pf.k0 = -1;
+}
+
 // One implicit double-shift step (all NT threads call) on the active rows l..i
-// of the m x m LDS matrix T; updates span all of T and Q's columns.
-__device__ __forceinline__ void lds_francis(double *T, int ldt, double *Q, int ldq, int m, int l, int i, double tr, double det) {
-    __shared__ double rq[2][3][FB];
+// of the m x m LDS matrix T; updates span all of T and Q's columns, except the
+// far field of the last batch, which is left pending in pf.
+__device__ __forceinline__ void lds_francis(double *T, int ldt, double *Q, int ldq, int m, int l, int i, double tr, double det,
+                                            FarPending &pf, double (*rq)[3][FB]) {
     const int tid = threadIdx.x, wave = tid / LANES;
     PROF_CNT(4, i - l);
+    {
+        const int k1 = (l + FB < i) ? l + FB : i;
+        const int cnear = (k1 + 1 < m - 1) ? k1 + 1 : m - 1;
+        if (pf.k0 >= 0 && cnear >= pf.k0) far_flush(T, ldt, Q, ldq, m, pf, rq);
+    }
     double x0 = 0.0, x1 = 0.0, x2 = 0.0;
-    int pk0 = -1, pnb = 0, pcnear = 0, pb = 0, cb = 0;
+    bool carried = pf.k0 >= 0;  // the previous sweep's last batch, for waves 1-3
+    int pk0 = pf.k0, pnb = pf.nb, pcnear = pf.cnear, pb = pf.buf, cb = carried ? pf.buf ^ 1 : 0;
     for (int k0 = l; k0 <= i - 1; k0 += FB) {
         const int k1 = (k0 + FB < i) ? k0 + FB : i;
         const int cnear = (k1 + 1 < m - 1) ? k1 + 1 : m - 1;
         if (wave == 0) {
             PROF_T(pa);
-            if (pk0 >= 0 && cnear > pcnear)  // previous batch on the columns entering the near field
+            if (pk0 >= 0 && !carried && cnear > pcnear)  // previous batch on the columns entering the near field
                 far_apply(T, ldt, Q, ldq, m, pk0, pnb, pcnear + 1, cnear, 0, false, rq[pb][0], rq[pb][1], rq[pb][2],
                           tid, LANES);
             near_steps(T, ldt, l, i, k0, k1, cnear, tr, det, rq[cb][0], rq[cb][1], rq[cb][2], x0, x1, x2);
             PROF_ADD(0, pa);
         } else if (pk0 >= 0) {
-            far_apply(T, ldt, Q, ldq, m, pk0, pnb, cnear + 1, m - 1, pk0, true, rq[pb][0], rq[pb][1], rq[pb][2],
+            // a carried batch's near field is complete: all of its far field here
+            const int c_lo = carried ? pcnear + 1 : cnear + 1;
+            far_apply(T, ldt, Q, ldq, m, pk0, pnb, c_lo, m - 1, pk0, true, rq[pb][0], rq[pb][1], rq[pb][2],
                       tid - LANES, NT - LANES);
         }
         PROF_T(pw);
         __syncthreads();
         PROF_ADD(1, pw);
+        carried = false;
         pk0 = k0;
         pnb = k1 - k0;
         pcnear = cnear;
         pb = cb;
         cb ^= 1;
     }
-    PROF_T(pf);
-    if (pk0 >= 0)
-        far_apply(T, ldt, Q, ldq, m, pk0, pnb, pcnear + 1, m - 1, pk0, true, rq[pb][0], rq[pb][1], rq[pb][2], tid, NT);
-    __syncthreads();
-    PROF_ADD(2, pf);
+    pf.k0 = pk0;
+    pf.nb = pnb;
+    pf.cnear = pcnear;
+    pf.buf = pb;
 }
 
 // Double-shift QR iteration on the m x m LDS matrix T (upper Hessenberg) with Q
@@ -303,7 +334,9 @@ __device__ __forceinline__ void lds_francis(double *T, int ldt, double *Q, int l
 // maxit iterations.  *iters receives the iteration count.
 __device__ __forceinline__ int lds_small_qr(double *T, int ldt, double *Q, int ldq, int m, double hnorm, double smlnum, int maxit,
                             int *iters) {
+    __shared__ double rq[2][3][FB];
     const int lane = threadIdx.x & (LANES - 1);
+    FarPending pf{-1, 0, 0, 0};
     int i = m - 1, its = 0, total = 0;
     while (i >= 0) {
         PROF_T(pe);
@@ -329,17 +362,23 @@ __device__ __forceinline__ int lds_small_qr(double *T, int ldt, double *Q, int l
             continue;
         }
         if (l == i - 1) {
+            far_flush(T, ldt, Q, ldq, m, pf, rq);
             lds_standardise(T, ldt, Q, ldq, m, i - 1);
             i -= 2;
             its = 0;
             continue;
         }
         if (total >= maxit) {
+            far_flush(T, ldt, Q, ldq, m, pf, rq);
             *iters = total;
             return i + 1;
         }
         ++total;
         ++its;
+        // the shift inputs: T(i-1, i) is the only one off the two diagonals
+        if (pf.k0 >= 0 && ((i - 1 < pf.k0 && i >= pf.k0 && i <= pf.k0 + pf.nb + 1) ||
+                           (i - 1 >= pf.k0 && i - 1 <= pf.k0 + pf.nb + 1 && i > pf.cnear)))
+            far_flush(T, ldt, Q, ldq, m, pf, rq);
         double tr, det;
         if (its == 10 || its == 20) {
             const double s = fabs(AT(T, ldt, i, i - 1)) + fabs(AT(T, ldt, i - 1, i - 2));
@@ -353,8 +392,9 @@ __device__ __forceinline__ int lds_small_qr(double *T, int ldt, double *Q, int l
             det = a * d - b * c;
         }
         __syncthreads();  // every wave has read the shift inputs before wave 0 writes
-        lds_francis(T, ldt, Q, ldq, m, l, i, tr, det);
+        lds_francis(T, ldt, Q, ldq, m, l, i, tr, det, pf, rq);
     }
+    far_flush(T, ldt, Q, ldq, m, pf, rq);
     *iters = total;
     return 0;
 }
