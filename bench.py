@@ -547,6 +547,7 @@ def batched_leg(args, dev):
         times.append(e0.elapsed_time(e1) / 1000.0)
         print(f"[bench] batched step {k} {times[-1] * 1e3:.1f} ms", file=sys.stderr, flush=True)
     info = call.info.cpu().numpy()
+    flops = binding.batched_flops()  # counted on the device by the last replay
     worst_be = worst_oe = 0.0
     for h0, S, Z in zip(H0, call.Hs, call.Zs):
         n = h0.shape[0]
@@ -567,6 +568,14 @@ def batched_leg(args, dev):
         "worst_backward_error_over_n_eps": round(worst_be, 4),
         "worst_orthogonality_over_n_eps": round(worst_oe, 4),
         "tuned_table": tuned,
+        "flops_algorithmic_per_batch": flops,
+        "gflops_algorithmic": round(flops / sec / 1e9, 1),
+        # one problem per workgroup, each a latency-bound chain on its compute
+        # unit: the FP64 vector peak of the chip is the roof it is measured against
+        "roofline": {"kernel": "k_batched", "bound": "alu", "achieved": round(flops / sec / 1e12, 4),
+                     "peak": 78.6, "unit": "TFLOP/s", "frac": float(f"{flops / sec / 78.6e12:.3g}"),
+                     "traffic": None, "avg_launch_us": round(sec * 1e6, 1), "flops_per_launch": flops,
+                     "note": "method's operation count, counted on the device by the batched kernel"},
     }
     if args.plain_loop:
         t_plain = 0.0

@@ -163,6 +163,21 @@ int neig_schur(int n, double *H, int ldh, double *Z, int ldz, double *wr, double
 int neig_schur_batched(int batch, const int *n, double *const *H, const int *ldh, double *const *Z, const int *ldz,
                        double *const *wr, double *const *wi, int *info, hipStream_t stream);
 
+/*
+ * neig_batched_flops -- the method's own floating-point operation count for
+ * the last neig_schur_batched call on the current device, counted on the
+ * device by the batched kernel (Section 3.2's steps: 10 m^3 per AED window or
+ * small block brought to Schur form in LDS, 2 m^2 for every row or column of H
+ * and Z its orthogonal factor is applied to, 20 n per bulge position of a
+ * sweep; the same formulas as neig_stats.alg_flops of the single-matrix path).
+ * The count is reset by each call's first kernel, so a graph replay counts
+ * its own work.  Waits for the device to finish, then copies the count to
+ * *flops (host).  neig_schur_batched_noalloc keeps its own count in its fixed
+ * array; this call does not read it.  Returns 0, -1 for a null pointer, or
+ * <= -100 for a HIP error (-100 - hipError_t).
+ */
+int neig_batched_flops(double *flops);
+
 /* Largest batch one neig_schur_batched_noalloc call takes. */
 #define NEIG_BATCH_NOALLOC_MAX 4096
 

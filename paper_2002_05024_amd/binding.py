@@ -132,6 +132,8 @@ def load_library():
         fn = getattr(lib, name)
         fn.argtypes = args
         fn.restype = _i
+    lib.neig_batched_flops.argtypes = [_dp]
+    lib.neig_batched_flops.restype = _i
     lib.neig_set_batched_tune.argtypes = [_i, _ip, _ip, _ip, _ip, _ip]
     lib.neig_set_batched_tune.restype = _i
     lib.neig_get_batched_tune.argtypes = [_ip, _ip, _ip, _ip, _ip, _ip]
@@ -337,6 +339,14 @@ def schur_batched(Hs, Zs=None, stream=None):
     call = batched_tables(Hs, Zs)
     launch_batched(call, stream)
     return call
+
+
+def batched_flops() -> float:
+    """neig_batched_flops: the method's operation count of the last
+    neig_schur_batched call on the current device (waits for the device)."""
+    out = ctypes.c_double(0.0)
+    _raise("neig_batched_flops", load_library().neig_batched_flops(ctypes.byref(out)))
+    return out.value
 
 
 def schur_batched_noalloc(Hs, Zs=None, stream=None):

@@ -31,7 +31,9 @@ struct BArgs {
     const BProb *probs;
     const int *order;   // processing order (largest problems first)
     int nprob;
-    int *next;          // work counter, zero before the launch
+    int *next;          // work counter, zero before the launch; next + 2 (8-byte
+                        // aligned) holds the launch's algorithmic flop count
+                        // (a double), also zeroed by k_batched_pack
     int *info;          // per problem, in the caller's order
     int bucket_hi[B_NBUCKET];  // problems with n <= bucket_hi[b] use tune[b]
     BTune tune[B_NBUCKET];
@@ -397,7 +399,11 @@ __device__ __forceinline__ int pick_shifts_dev(const double *rr, const double *r
 
 // ---------------------------------------------------------------- one problem
 
-__device__ __forceinline__ int solve_one(const BProb &P, const BTune &tu, const BArgs &A, double *lds) {
+// *flops receives the method's own operation count for this problem (the same
+// formulas as the single-matrix path's neig_stats.alg_flops: 10 m^3 per window
+// or small block solved in LDS, 2 m^2 per row or column its factor is applied
+// to, 20 n per bulge position of a sweep); every thread holds the same value.
+__device__ __forceinline__ int solve_one(const BProb &P, const BTune &tu, const BArgs &A, double *lds, double *flops) {
     __shared__ double s_rr[NEIG_SMALL_MAX], s_ri[NEIG_SMALL_MAX];
     __shared__ double s_ptr[B_MAX_BULGES * 4], s_pdet[B_MAX_BULGES * 4];
     __shared__ int s_nsh;
@@ -413,6 +419,7 @@ __device__ __forceinline__ int solve_one(const BProb &P, const BTune &tu, const 
     const int maxit = A.maxit_factor * (n > 10 ? n : 10);
     int info = 0;
     int kbot = n - 1, total = 0, ndefl = 0;
+    double fl = 0.0;
     while (kbot >= 0) {
         const int ktop = wg_scan(H, ldh, kbot, hnorm, smlnum);
         const int m = kbot - ktop + 1;
@@ -431,6 +438,7 @@ __device__ __forceinline__ int solve_one(const BProb &P, const BTune &tu, const 
                 __syncthreads();
                 double *stage = pick_stage(T, (size_t)m * ld, Q + (size_t)m * ld, m);
                 wg_block_updates(H, ldh, Z, ldz, n, ktop, kbot, Q, ld, stage);
+                fl += 10.0 * m * (double)m * m + 2.0 * m * (double)m * (ktop + (n - kbot - 1) + n);
                 if (bad > 0) {
                     info = ktop + bad;
                     break;
@@ -454,6 +462,8 @@ __device__ __forceinline__ int solve_one(const BProb &P, const BTune &tu, const 
         lds_load_block(H, ldh, kwtop, nw, T, ld, V, ld);
         const AedOut o = aed_core(T, V, ld, x, nw, s, hnorm, smlnum, A.criterion, 30 * (nw > 10 ? nw : 10), s_rr,
                                   s_ri);
+        fl += 10.0 * nw * (double)nw * nw;
+        if (o.nd > 0) fl += 2.0 * nw * (double)nw * (kwtop + (n - kbot - 1) + n);
         if (o.nd > 0) {
             for (int idx = tid; idx < nw * nw; idx += NT) {
                 const int i = idx % nw, j = idx / nw;
@@ -512,6 +522,7 @@ __device__ __forceinline__ int solve_one(const BProb &P, const BTune &tu, const 
         // sweep: chains of at most B_MAX_BULGES bulges, one after another
         const int nbulge = s_nsh / 2;
         const int wmax = tu.wchase;
+        fl += 20.0 * n * (double)nbulge * (kbot - ktop);
         for (int c0 = 0; c0 < nbulge; c0 += B_MAX_BULGES) {
             const int nb = (nbulge - c0 < B_MAX_BULGES) ? nbulge - c0 : B_MAX_BULGES;
             const int tend = kbot - 1 - ktop + 3 * (nb - 1);
@@ -588,6 +599,7 @@ __device__ __forceinline__ int solve_one(const BProb &P, const BTune &tu, const 
         }
     }
     __syncthreads();
+    *flops = fl;
     return info;
 }
 
@@ -605,8 +617,12 @@ extern "C" __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per
         if (P.pad) continue;  // rejected by k_batched_pack (uniform across the workgroup)
         int b = 0;
         while (b + 1 < B_NBUCKET && P.n > A.bucket_hi[b]) ++b;
-        const int info = solve_one(P, A.tune[b], A, lds);
-        if (threadIdx.x == 0) A.info[p] = info;
+        double fl = 0.0;
+        const int info = solve_one(P, A.tune[b], A, lds, &fl);
+        if (threadIdx.x == 0) {
+            A.info[p] = info;
+            atomicAdd((double *)(A.next + 2), fl);
+        }
         __syncthreads();
     }
 }
@@ -624,7 +640,10 @@ extern "C" __global__ void __launch_bounds__(256) k_batched_pack(BProb *out, int
     __shared__ int sk[256];
     const int b = blockIdx.x * blockDim.x + threadIdx.x;
     const bool mine = b < batch;
-    if (b == 0) *next = 0;
+    if (b == 0) {
+        *next = 0;
+        *(double *)(next + 2) = 0.0;  // the launch's flop count
+    }
     int key = -1;
     if (mine) {
         BProb p;

@@ -191,7 +191,7 @@ DeviceWs &workspace() {
     ck(hipMalloc((void **)&w.ist, kStatusInts * sizeof(int)));
     ck(hipMalloc((void **)&w.bprob, (size_t)NEIG_BATCH_MAX * sizeof(BProb)));
     ck(hipMalloc((void **)&w.border, (size_t)NEIG_BATCH_MAX * sizeof(int)));
-    ck(hipMalloc((void **)&w.bnext, sizeof(int)));
+    ck(hipMalloc((void **)&w.bnext, 4 * sizeof(int)));  // work counter, pad, flop count (a double)
     ck(hipMalloc((void **)&w.theta, (size_t)MLP_NPARAM * sizeof(float)));
     ck(hipMalloc((void **)&w.pol_out, 32 * sizeof(float)));
     ck(hipHostMalloc((void **)&w.h_pol_out, 32 * sizeof(float), hipHostMallocDefault));
@@ -1598,6 +1598,19 @@ extern "C" int neig_schur_batched(int batch, const int *n, double *const *H, con
         DeviceWs &ws = workspace();
         launch_batched_pair(batch, n, H, ldh, Z, ldz, wr, wi, info, ws.bprob, ws.border, ws.bnext, ws.small_max,
                             ws.chase_max, ws.cus, stream);
+    } catch (const HipFail &f) {
+        return -100 - (int)f.e;
+    }
+    return 0;
+}
+
+extern "C" int neig_batched_flops(double *flops) {
+    if (!flops) return -1;
+    std::lock_guard<std::mutex> lock(g_mutex);
+    try {
+        DeviceWs &ws = workspace();
+        ck(hipDeviceSynchronize());
+        ck(hipMemcpy(flops, ws.bnext + 2, sizeof(double), hipMemcpyDeviceToHost));
     } catch (const HipFail &f) {
         return -100 - (int)f.e;
     }

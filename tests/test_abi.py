@@ -106,6 +106,8 @@ def test_batched_argument_errors_without_gpu_work():
     assert lib.neig_schur_batched_noalloc(4097, *([None] * 9)) == -1  # above its fixed capacity
     assert lib.neig_schur_batched_noalloc(0, *([None] * 9)) == 0
     assert lib.neig_schur_batched_noalloc(3, *([None] * 9)) == -2
+    lib.neig_batched_flops.argtypes = [ctypes.c_void_p]
+    assert lib.neig_batched_flops(None) == -1
 
 
 def test_product_path_has_no_cpu_fallback():

@@ -160,3 +160,26 @@ def test_batched_graph_capture_replays(neig):
         for i, (a, b) in enumerate(zip(got, ref)):
             assert torch.equal(a, b), (rep, i)
         assert np.all(call.info.cpu().numpy() == 0)
+
+
+def test_batched_flop_count(neig):
+    """The batched kernel counts the method's operations on the device: integer
+    counts, so a batch [A, B, A] counts exactly twice A's work plus B's, every
+    problem at least its final 10 m^3 Schur form, and each call (a replayed
+    graph included) counts only its own work."""
+    import torch
+
+    A, B = make_batch([180, 140], 41)[0]
+    counts = {}
+    for tag, Hs in (("A", [A]), ("B", [B]), ("ABA", [A, B, A])):
+        c = neig.schur_batched([to_dev(H) for H in Hs])
+        torch.cuda.synchronize()
+        assert np.all(c.info.cpu().numpy() == 0)
+        counts[tag] = neig.batched_flops()
+        say(f"  flops {tag}: {counts[tag]:.6g}")
+    assert counts["A"] > 10 * 180.0 ** 3 / 8 and counts["B"] > 0
+    assert counts["ABA"] == 2 * counts["A"] + counts["B"]
+    # a second call of the same batch counts the same, not the sum of both
+    c = neig.schur_batched([to_dev(A)])
+    torch.cuda.synchronize()
+    assert neig.batched_flops() == counts["A"]
