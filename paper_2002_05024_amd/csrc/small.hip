@@ -705,6 +705,43 @@ __device__ __forceinline__ bool sylv22_closed(const double (&B)[4][4], double (&
     return isfinite(x00) && isfinite(x01) && isfinite(x10) && isfinite(x11);
 }
 
+// Closed-form solve of the Sylvester equation when one block is 1x1: for
+// (P, Q) = (1, 2) it reads X (a I - C) = R (X a row), for (2, 1) it reads
+// (A - c I) X = R (X a column); either is one 2 x 2 system, solved by its
+// adjugate, with one step of residual correction.  Returns false when the
+// system is singular or the result is not finite (the caller then solves by
+// complete pivoting).
+template <int P, int Q>
+__device__ __forceinline__ bool sylv12_closed(const double (&B)[P + Q][P + Q], double (&X)[2]) {
+    static_assert(P * Q == 2, "one 1x1 and one 2x2 block");
+    double m00, m01, m10, m11, r0, r1;
+    if constexpr (P == 1) {  // [x0 x1] M = [r0 r1], M = a I - C
+        m00 = B[0][0] - B[1][1]; m01 = -B[1][2]; m10 = -B[2][1]; m11 = B[0][0] - B[2][2];
+        r0 = B[0][1]; r1 = B[0][2];
+    } else {  // M [x0; x1] = [r0; r1], M = A - c I
+        m00 = B[0][0] - B[2][2]; m01 = B[0][1]; m10 = B[1][0]; m11 = B[1][1] - B[2][2];
+        r0 = B[0][2]; r1 = B[1][2];
+    }
+    const double det = m00 * m11 - m01 * m10;
+    if (!(fabs(det) > 0.0)) return false;
+    const double rd = 1.0 / det;
+    double x0 = 0.0, x1 = 0.0, e0 = r0, e1 = r1;
+#pragma unroll
+    for (int pass = 0; pass < 2; ++pass) {
+        if constexpr (P == 1) {  // row vector: e M^-1
+            x0 += (e0 * m11 - e1 * m10) * rd;
+            x1 += (e1 * m00 - e0 * m01) * rd;
+            if (pass == 0) { e0 = r0 - (x0 * m00 + x1 * m10); e1 = r1 - (x0 * m01 + x1 * m11); }
+        } else {  // column vector: M^-1 e
+            x0 += (m11 * e0 - m01 * e1) * rd;
+            x1 += (m00 * e1 - m10 * e0) * rd;
+            if (pass == 0) { e0 = r0 - (m00 * x0 + m01 * x1); e1 = r1 - (m10 * x0 + m11 * x1); }
+        }
+    }
+    X[0] = x0; X[1] = x1;
+    return isfinite(x0) && isfinite(x1);
+}
+
 // Orthogonal Qm (N x N) and the swapped block Bn = Qm^T B Qm for block sizes (P, Q).
 template <int P, int Q>
 __device__ __forceinline__ bool swap_transform(const double (&B)[P + Q][P + Q], double (&Qm)[P + Q][P + Q],
@@ -737,6 +774,9 @@ __device__ __forceinline__ bool swap_transform(const double (&B)[P + Q][P + Q], 
             double Xc[4];
             if (sylv22_closed(B, Xc) && swap_from_x<2, 2>(B, Xc, bnorm, Qm, Bn)) return true;
             PROF_CNT(7, 1);  // the closed form was rejected: 4 x 4 solve
+        } else {
+            double Xc[2];
+            if (sylv12_closed<P, Q>(B, Xc) && swap_from_x<P, Q>(B, Xc, bnorm, Qm, Bn)) return true;
         }
         constexpr int K = P * Q;
         double M[K][K], rhs[K], X[K];
