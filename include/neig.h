@@ -75,7 +75,11 @@ typedef struct neig_params {
                       window too (the same step on the flipped block J B^T J, which is
                       upper Hessenberg again), both in one launch on two compute units;
                       1: the trailing window only                                        */
-    int reserved[1];
+    int overlap;   /* sweeps: the updates of each chase step are split into the entries the
+                      next step's windows cover, applied on the call's stream, and the
+                      rest, applied on a second stream beside the next chase launch
+                      (Section 3.2: updates run concurrently with the chase);
+                      0: for orders of at least 8192; 1: always; 2: never               */
 } neig_params;
 
 /* Largest AED window.  Windows of at most 96 rows are solved in one workgroup's

@@ -44,7 +44,7 @@ class Params(ctypes.Structure):
         ("rec_nw", _i),
         ("rec_ns", _i),
         ("aed_ends", _i),
-        ("reserved", _i * 1),
+        ("overlap", _i),
     ]
 
 
@@ -532,7 +532,7 @@ def set_params(**kw) -> None:
     p = Params()
     lib.neig_get_params(ctypes.byref(p))
     for k, v in kw.items():
-        if not hasattr(p, k) or k == "reserved":
+        if not hasattr(p, k):
             raise NeigError(f"unknown parameter {k}")
         setattr(p, k, int(v))
     rc = lib.neig_set_params(ctypes.byref(p))
@@ -544,7 +544,7 @@ def get_params() -> dict:
     lib = load_library()
     p = Params()
     lib.neig_get_params(ctypes.byref(p))
-    return {f: getattr(p, f) for f, _ in Params._fields_ if f != "reserved"}
+    return {f: getattr(p, f) for f, _ in Params._fields_}
 
 
 def get_stats() -> dict:

@@ -79,6 +79,7 @@ std::vector<PolicySample> g_policy_log;
 
 constexpr int kMaxDevices = 64;
 constexpr int kStatusInts = 64;
+constexpr int kOverlapMinN = 8192;  // automatic overlap of sweep updates from this order on
 
 template <class T>
 void grow(T **p, size_t *cap, size_t need) {
@@ -140,6 +141,10 @@ struct DeviceWs {
     int *rstat = nullptr; size_t rstat_cap = 0;
     int *h_rstat = nullptr; size_t h_rstat_cap = 0;
     HrdState *hrd_st = nullptr;
+    // a second stream for a sweep's off-diagonal updates, which run beside the
+    // next chase launch, and the events that order it with the caller's stream
+    hipStream_t ust = nullptr;
+    hipEvent_t ev_near = nullptr, ev_far = nullptr, ev_join = nullptr;
 };
 
 DeviceWs g_ws[kMaxDevices];
@@ -196,6 +201,8 @@ DeviceWs &workspace() {
     ck(hipMalloc((void **)&w.pol_out, 32 * sizeof(float)));
     ck(hipHostMalloc((void **)&w.h_pol_out, 32 * sizeof(float), hipHostMallocDefault));
     grow_host(&w.h_ist, &w.h_ist_cap, (size_t)kStatusInts);
+    ck(hipStreamCreateWithFlags(&w.ust, hipStreamNonBlocking));
+    for (hipEvent_t *e : {&w.ev_near, &w.ev_far, &w.ev_join}) ck(hipEventCreateWithFlags(e, hipEventDisableTiming));
     w.ready = true;
     return w;
 }
@@ -212,6 +219,9 @@ void free_workspace(DeviceWs &w) {
                     (void *)w.h_rwin, (void *)w.h_rstat})
         if (p) (void)hipHostFree(p);
     for (hipEvent_t e : w.events) (void)hipEventDestroy(e);
+    for (hipEvent_t e : {w.ev_near, w.ev_far, w.ev_join})
+        if (e) (void)hipEventDestroy(e);
+    if (w.ust) (void)hipStreamDestroy(w.ust);
     w = DeviceWs();
 }
 
@@ -292,14 +302,19 @@ class Solver {
 
     template <class F>
     void timed(int kind, F &&launch) {
+        timed_on(st_, kind, launch);
+    }
+
+    template <class F>
+    void timed_on(hipStream_t s, int kind, F &&launch) {
         if (!p_.timing) {
             launch();
             return;
         }
         hipEvent_t a = next_event(), b = next_event();
-        ck(hipEventRecord(a, st_));
+        ck(hipEventRecord(a, s));
         launch();
-        ck(hipEventRecord(b, st_));
+        ck(hipEventRecord(b, s));
         marks_.push_back({kind, a, b});
     }
 
@@ -374,10 +389,12 @@ class Solver {
         int ldc, ldu, w, len, side;
     };
 
-    void run_updates(const std::vector<Task> &all) {
+    void run_updates(const std::vector<Task> &all) { run_updates(all, st_); }
+
+    void run_updates(const std::vector<Task> &all, hipStream_t s) {
         std::vector<Task> tasks, wide;
         for (const Task &t : all) (t.w > UPD_WMAX ? wide : tasks).push_back(t);
-        run_updates_wide(wide);
+        run_updates_wide(wide, s);
         size_t i = 0;
         while (i < tasks.size()) {
             UpdArgs a;
@@ -395,33 +412,33 @@ class Solver {
             }
             a.ntask = nt;
             if (nt == 0 || tiles == 0) continue;
-            launch_update_p(a, tiles, (wmaxp + 15) / 16);
+            launch_update_p(a, tiles, (wmaxp + 15) / 16, s);
         }
     }
 
-    void launch_update_p(const UpdArgs &a, int nslice, int nrt) {
+    void launch_update_p(const UpdArgs &a, int nslice, int nrt, hipStream_t s) {
         switch (nrt) {
-            case 1: launch_update_nrt<1>(a, nslice); break;
-            case 2: launch_update_nrt<2>(a, nslice); break;
-            case 3: launch_update_nrt<3>(a, nslice); break;
-            case 4: launch_update_nrt<4>(a, nslice); break;
-            case 5: launch_update_nrt<5>(a, nslice); break;
-            default: launch_update_nrt<6>(a, nslice); break;
+            case 1: launch_update_nrt<1>(a, nslice, s); break;
+            case 2: launch_update_nrt<2>(a, nslice, s); break;
+            case 3: launch_update_nrt<3>(a, nslice, s); break;
+            case 4: launch_update_nrt<4>(a, nslice, s); break;
+            case 5: launch_update_nrt<5>(a, nslice, s); break;
+            default: launch_update_nrt<6>(a, nslice, s); break;
         }
     }
 
     template <int NRT>
-    void launch_update_nrt(const UpdArgs &a, int nslice) {
+    void launch_update_nrt(const UpdArgs &a, int nslice, hipStream_t s) {
         const int grid = std::min(nslice, ws_.cus * update_p_occupancy<NRT>(ws_));
-        timed(kUpdate, [&] {
-            hipLaunchKernelGGL(k_update_p<NRT>, dim3(grid), dim3(64 * NRT), update_p_lds(NRT), st_, a, nslice);
+        timed_on(s, kUpdate, [&] {
+            hipLaunchKernelGGL(k_update_p<NRT>, dim3(grid), dim3(64 * NRT), update_p_lds(NRT), s, a, nslice);
             ck(hipGetLastError());
         });
     }
 
     // tasks with factors of order UPD_WMAX+1 .. UPW_WMAX: U^T streamed from L2,
     // only the strip's slice staged in LDS
-    void run_updates_wide(const std::vector<Task> &tasks) {
+    void run_updates_wide(const std::vector<Task> &tasks, hipStream_t s) {
         size_t i = 0;
         while (i < tasks.size()) {
             UpdArgs a;
@@ -443,8 +460,8 @@ class Solver {
             // side 0 stages wp x UPW_SLICE with leading dimension wp + 1, side 1
             // UPW_SLICE x wp with leading dimension UPW_SLICE + 1
             const size_t lds = (size_t)(wmaxp + 1) * (UPW_SLICE + 1) * sizeof(double);
-            timed(kUpdate, [&] {
-                hipLaunchKernelGGL(k_update_wide, dim3(tiles), dim3(UPW_THREADS), lds, st_, a);
+            timed_on(s, kUpdate, [&] {
+                hipLaunchKernelGGL(k_update_wide, dim3(tiles), dim3(UPW_THREADS), lds, s, a);
                 ck(hipGetLastError());
             });
         }
@@ -677,6 +694,45 @@ class Solver {
         int r0, r1, t0, t1;
     };
 
+    // Update tasks of one part of a sweep step: left strips (rows of a window,
+    // columns right of it), right strips of H (rows above a window, its
+    // columns) and the Z tasks, with the H rectangles they cover.
+    struct Rect {
+        int r0, r1, c0, c1;
+    };
+    struct Parts {
+        std::vector<Task> l, r, z;
+        std::vector<Rect> lr, rr;
+        void left(double *H, int ldh, const double *ut, int ldut, int r0, int r1, int c0, int c1) {
+            l.push_back({H + r0 + (size_t)c0 * ldh, ut, ldh, ldut, r1 - r0 + 1, c1 - c0 + 1, 0});
+            lr.push_back({r0, r1, c0, c1});
+        }
+        void right(double *H, int ldh, const double *ut, int ldut, int a, int b, int c0, int c1) {
+            r.push_back({H + a + (size_t)c0 * ldh, ut, ldh, ldut, c1 - c0 + 1, b - a + 1, 1});
+            rr.push_back({a, b, c0, c1});
+        }
+        bool cross() const {  // does a left strip meet a right strip?
+            for (const Rect &x : lr)
+                for (const Rect &y : rr)
+                    if (x.r0 <= y.r1 && y.r0 <= x.r1 && x.c0 <= y.c1 && y.c0 <= x.c1) return true;
+            return false;
+        }
+    };
+
+    // One launch when no left strip meets a right strip, else every left strip
+    // first (each pair commutes, but not within one launch).
+    void run_parts(Parts &p, hipStream_t s) {
+        if (!p.cross()) {
+            p.l.insert(p.l.end(), p.r.begin(), p.r.end());
+            p.l.insert(p.l.end(), p.z.begin(), p.z.end());
+            run_updates(p.l, s);
+        } else {
+            run_updates(p.l, s);
+            p.r.insert(p.r.end(), p.z.begin(), p.z.end());
+            run_updates(p.r, s);
+        }
+    }
+
     void sweep(int ktop, int kbot, const std::vector<Eig> &sh) {
         double t0ms = now_ms();
         const int nbulge = (int)sh.size() / 2;
@@ -693,7 +749,9 @@ class Solver {
         const int nchain = (nbulge + nbc - 1) / nbc;
         const int wmax = wchase_;
         const int ldut = wmax;
-        grow(&ws_.ut, &ws_.ut_cap, (size_t)std::min(nchain, NEIG_MAX_CHAINS) * ldut * ldut);
+        // two sets of U^T slots, used by alternate steps
+        const size_t slot = (size_t)std::min(nchain, NEIG_MAX_CHAINS) * ldut * ldut;
+        grow(&ws_.ut, &ws_.ut_cap, 2 * slot);
         std::vector<std::vector<Win>> wins(nchain);
         std::vector<int> nbs(nchain);
         for (int c = 0; c < nchain; ++c) {
@@ -709,8 +767,28 @@ class Solver {
                 t = t1;
             }
         }
+        // With overlap on, the updates of each step are split in two parts: the
+        // near part (the entries of H that the next step's windows may cover,
+        // rows and columns lo..hi) runs on the caller's stream right after the
+        // step's chase launch, and the far part (the rest of H, all of Z) on
+        // the update stream, beside the next step's chase launch; the next
+        // step's near part waits for it (their left strips share rows).  The
+        // windows of the next step are each chain's next window or a subset of
+        // them.  Where one window's left strip crosses another's right strip
+        // (rows of a window behind, columns of one ahead), the two updates
+        // commute only as wholes, so that block is never split between the
+        // parts: a left strip that reaches the next windows' rows keeps every
+        // window's columns that start at or before hi in its near part, and a
+        // right strip is split only if its window's columns start at or before
+        // hi.
+        const bool ovl = p_.overlap == 1 || (p_.overlap == 0 && n_ >= kOverlapMinN);
+        if (ovl) {
+            ck(hipEventRecord(ws_.ev_join, st_));
+            ck(hipStreamWaitEvent(ws_.ust, ws_.ev_join, 0));
+        }
         std::vector<size_t> idx(nchain, 0);
-        for (;;) {
+        int step = 0;
+        for (;; ++step) {
             ChaseArgs ca;
             std::memset(&ca, 0, sizeof(ca));
             ca.ktop = ktop; ca.kbot = kbot; ca.nbc = nbc; ca.ldut = ldut;
@@ -741,30 +819,54 @@ class Solver {
             if (!any_left) break;
             if (nact == 0) throw HipFail{hipErrorUnknown};  // schedule cannot stall
             ca.nwin = nact;
+            double *uts = ws_.ut + (size_t)(step & 1) * slot;
             timed(kChase, [&] {
-                hipLaunchKernelGGL(k_chase, dim3(nact), dim3(CHASE_THREADS), lds, st_, H_, ldh_, ws_.poly, ws_.ut,
-                                   ca);
+                hipLaunchKernelGGL(k_chase, dim3(nact), dim3(CHASE_THREADS), lds, st_, H_, ldh_, ws_.poly, uts, ca);
                 ck(hipGetLastError());
             });
-            std::vector<Task> left, right;
+            // rows and columns lo..hi hold every window of the next step
+            int lo = n_, hi = -1;
+            if (ovl)
+                for (int c = 0; c < nchain; ++c)
+                    if (idx[c] < wins[c].size()) {
+                        const Win &wn = wins[c][idx[c]];
+                        lo = std::min(lo, wn.r0 > 0 ? wn.r0 - 1 : 0);
+                        hi = std::max(hi, wn.r1);
+                    }
+            int hi_left = hi;  // near columns of the left strips
+            for (int k = 0; k < nact; ++k)
+                if (ca.win[k].r0 <= hi) hi_left = std::max(hi_left, ca.win[k].r1);
+            Parts near, far;
             for (int k = 0; k < nact; ++k) {
                 const ChaseWin &cw = ca.win[k];
-                const double *ut = ws_.ut + (size_t)k * ldut * ldut;
+                const double *ut = uts + (size_t)k * ldut * ldut;
                 const int w = cw.r1 - cw.r0 + 1;
                 const int b0 = cw.r0 > 0 ? cw.r0 - 1 : 0;
-                if (cw.r1 + 1 < n_)
-                    left.push_back({H_ + cw.r0 + (size_t)(cw.r1 + 1) * ldh_, ut, ldh_, ldut, w, n_ - cw.r1 - 1, 0});
-                if (b0 > 0) right.push_back({H_ + (size_t)cw.r0 * ldh_, ut, ldh_, ldut, w, b0, 1});
-                right.push_back({Z_ + (size_t)cw.r0 * ldz_, ut, ldz_, ldut, w, n_, 1});
+                if (cw.r1 + 1 < n_) {  // rows r0..r1, columns r1+1..n-1: near up to column cm
+                    const int c0 = cw.r1 + 1;
+                    const int cm = (cw.r1 >= lo) ? std::min(std::max(hi_left, cw.r1), n_ - 1) : cw.r1;
+                    if (cm >= c0) near.left(H_, ldh_, ut, ldut, cw.r0, cw.r1, c0, cm);
+                    if (cm + 1 < n_) far.left(H_, ldh_, ut, ldut, cw.r0, cw.r1, cm + 1, n_ - 1);
+                }
+                if (b0 > 0) {  // rows 0..b0-1, columns r0..r1: near from row rm
+                    const int rm = (cw.r0 <= hi) ? std::min(lo, b0) : b0;
+                    if (rm < b0) near.right(H_, ldh_, ut, ldut, rm, b0 - 1, cw.r0, cw.r1);
+                    if (rm > 0) far.right(H_, ldh_, ut, ldut, 0, rm - 1, cw.r0, cw.r1);
+                }
+                far.z.push_back({Z_ + (size_t)cw.r0 * ldz_, ut, ldz_, ldut, w, n_, 1});
             }
-            if (nact == 1) {
-                left.insert(left.end(), right.begin(), right.end());
-                run_updates(left);
+            if (ovl) {
+                if (step > 0) ck(hipStreamWaitEvent(st_, ws_.ev_far, 0));
+                run_parts(near, st_);
+                ck(hipEventRecord(ws_.ev_near, st_));
+                ck(hipStreamWaitEvent(ws_.ust, ws_.ev_near, 0));
+                run_parts(far, ws_.ust);
+                ck(hipEventRecord(ws_.ev_far, ws_.ust));
             } else {
-                run_updates(left);
-                run_updates(right);
+                run_parts(far, st_);  // lo > hi: everything is in the far part
             }
         }
+        if (ovl && step > 0) ck(hipStreamWaitEvent(st_, ws_.ev_far, 0));
         stats_.sweeps++;
         stats_.shifts_used += 2 * nbulge;
         stats_.alg_flops += 20.0 * n_ * (double)nbulge * (kbot - ktop);
@@ -1874,6 +1976,8 @@ extern "C" int neig_set_params(const neig_params *p) {
     if (p->nw > NEIG_AED_MAX) return -2;
     if (p->rec_nw < 0 || p->rec_nw > NEIG_SMALL_MAX) return -13;
     if (p->rec_ns < 0 || p->rec_ns % 2) return -14;
+    if (p->aed_ends < 0 || p->aed_ends > 1) return -15;
+    if (p->overlap < 0 || p->overlap > 2) return -16;
     std::lock_guard<std::mutex> lock(g_mutex);
     g_params = *p;
     return 0;

@@ -45,6 +45,10 @@ def test_params_roundtrip_and_validation():
         binding.set_params(ns=3)  # odd shift count
     with pytest.raises(binding.NeigError):
         binding.set_params(deflation=5)
+    with pytest.raises(binding.NeigError):
+        binding.set_params(overlap=3)
+    with pytest.raises(binding.NeigError):
+        binding.set_params(aed_ends=2)
     binding.set_params(**before)
     assert binding.get_params() == before
 

@@ -152,6 +152,40 @@ def test_sweep_implicit_q(neig, n, ktop, kbot, nbul, chain, chase_w):
     assert np.linalg.norm(Hg - d[:, None] * Ho * d[None, :]) <= 1e-9 * nh
 
 
+@pytest.mark.parametrize("n,ktop,kbot,nbul,chain,chase_w", [
+    (600, 0, 599, 24, 16, 96),
+    (700, 10, 650, 32, 16, 96),
+    (1500, 0, 1499, 32, 8, 64),   # four chains of 8 in 64-row windows
+    (1200, 30, 1100, 40, 4, 40),  # ten chains of 4 on an interior block
+    (300, 0, 299, 6, 2, 16),      # many small windows
+])
+def test_sweep_overlap_matches_one_stream(neig, n, ktop, kbot, nbul, chain, chase_w):
+    """The sweep with each step's far updates on the second stream, beside the
+    next chase launch, gives the same H and Z, to the bit, as the sweep with
+    every update on the call's stream: the same products in the same order."""
+    say(f"sweep overlap n={n} [{ktop},{kbot}] bulges={nbul} chain={chain} w={chase_w}")
+    H = inputs.random_hessenberg(n, inputs.rng(91, n))
+    if ktop > 0:
+        H[ktop, ktop - 1] = 0.0
+    if kbot + 1 < n:
+        H[kbot + 1, kbot] = 0.0
+    z = [complex(20.0 + k, 3.0 + 0.5 * k) for k in range(nbul)]
+    shifts = np.array([v for c in z for v in (c, c.conjugate())])
+    out = {}
+    for ov in (2, 1):
+        neig.set_params(chain=chain, chase_w=chase_w, overlap=ov)
+        try:
+            Hd, Zd = to_dev(H), to_dev(np.eye(n))
+            neig.sweep(Hd, Zd, ktop, kbot, shifts.real, shifts.imag)
+        finally:
+            neig.set_params(chain=0, chase_w=0, overlap=0)
+        out[ov] = (to_host(Hd), to_host(Zd))
+    (H2, Z2), (H1, Z1) = out[2], out[1]
+    assert backward_error(H, H1, Z1) <= 50 * n * EPS
+    assert orthogonality(Z1) <= 50 * n * EPS
+    assert np.array_equal(H1, H2) and np.array_equal(Z1, Z2), (np.abs(H1 - H2).max(), np.abs(Z1 - Z2).max())
+
+
 # ---------------------------------------------------------------- one AED step
 
 @pytest.mark.parametrize("n,nw", [(120, 40), (200, 96)])
@@ -193,6 +227,31 @@ def test_schur_random_hessenberg(neig, n):
     be, oe = check_result(H, S, Z, wr, wi, info, f"random n={n}")
     frac = eigen_parity(H, wr, wi, f"random n={n}")
     say(f"  backward {be:.2e} orth {oe:.2e} unpinned {frac:.2f} stats {neig.get_stats()}")
+
+
+def test_schur_overlap_sweep_heavy(neig):
+    """A sweep-heavy whole reduction (Hessenberg form of a dense uniform[-1,1]
+    matrix, 64 shifts in chains of 8, 64-row chase windows) with the sweeps'
+    far updates on the second stream: a valid Schur form, and the same one, to
+    the bit, as with every update on the call's stream."""
+    n = 1500
+    say(f"schur overlap, dense uniform n={n}")
+    g = inputs.rng(inputs.FULL, 61)
+    H, _ = inputs.to_hessenberg(g.uniform(-1.0, 1.0, (n, n)))
+    res = {}
+    for ov in (2, 1):
+        neig.set_params(ns=64, nw=80, chain=8, chase_w=64, overlap=ov)
+        try:
+            res[ov] = run_gpu(neig, H)
+            st = neig.get_stats()
+        finally:
+            neig.set_params(ns=0, nw=0, chain=0, chase_w=0, overlap=0)
+        say(f"  overlap={ov}: sweeps {st['sweeps']} aeds {st['aeds']}")
+        assert st["sweeps"] > 0
+    S, Z, wr, wi, info = res[1]
+    check_result(H, S, Z, wr, wi, info, "overlap")
+    for a, b in zip(res[1], res[2]):
+        assert np.array_equal(a, b)
 
 
 @pytest.mark.parametrize("seed", [0, 1, 2, 3])
