@@ -7,7 +7,9 @@
 // step on the trailing window with a multishift sweep that uses the window's
 // undeflated Ritz values as shifts.  Each AED and each small solve ends with one
 // small device-to-host read of its status; sweeps are launched without
-// synchronisation.  All launches go to the caller's stream.
+// synchronisation.  Launches go to the caller's stream, except the far part of
+// a sweep step's updates, which runs on the library's second stream beside the
+// next chase launch; the caller's stream waits for it before the sweep ends.
 //
 // Also here: the batched entry points (descriptor packing and the persistent
 // solver of batched.hip), eigenvalue reordering (rounds of concurrent windows,
