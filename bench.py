@@ -202,6 +202,18 @@ def rooflines(stats):
             "avg_launch_us": round(upd_ms * 1000.0 / max(upd_n, 1), 2),
             "flops_per_launch": round(upd_fl / max(upd_n, 1), 1),
         }
+        far_ms = sum(s["gpu_update_far_ms"] for s in stats)
+        if far_ms > 0:
+            # the far parts of overlapped sweep steps, which run beside the next
+            # chase launch (included in the figures above)
+            far_fl = sum(s["gemm_flops_far"] for s in stats)
+            far_n = sum(s["n_update_far"] for s in stats)
+            fach = far_fl / (far_ms / 1000.0) / 1e12
+            out["roofline_update"]["far_part"] = {
+                "achieved": round(fach, 3), "frac": round(fach / FP64_MFMA_PEAK_TFLOPS, 4),
+                "launches": int(far_n), "avg_launch_us": round(far_ms * 1000.0 / max(far_n, 1), 2),
+                "flop_share": round(far_fl / max(upd_fl, 1.0), 4),
+            }
     ch_ms = sum(s["gpu_chase_ms"] for s in stats)
     ch_n = sum(s["n_chase"] for s in stats)
     ch_b = sum(s["chase_bytes"] for s in stats)

@@ -115,6 +115,9 @@ typedef struct neig_stats {
     double aeds_top, aed_top_deflated;  /* leading-window AED steps (counted in aeds too) and
                                            the eigenvalues they deflated                    */
     double aed_launches;  /* launches of the LDS AED kernel (one or two windows each)      */
+    /* the far parts of overlapped sweep steps (parameter overlap; counted in the
+       update totals above too): GPU time (timing = 1), launches, executed flops */
+    double gpu_update_far_ms, n_update_far, gemm_flops_far;
 } neig_stats;
 
 /*

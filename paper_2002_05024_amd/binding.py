@@ -90,6 +90,9 @@ class Stats(ctypes.Structure):
         ("aeds_top", ctypes.c_double),
         ("aed_top_deflated", ctypes.c_double),
         ("aed_launches", ctypes.c_double),
+        ("gpu_update_far_ms", ctypes.c_double),
+        ("n_update_far", ctypes.c_double),
+        ("gemm_flops_far", ctypes.c_double),
     ]
 
 

@@ -285,7 +285,7 @@ class Solver {
     neig_stats stats_;
 
     // ---- timing mode: HIP events around launches, per kernel class ---------
-    enum Kind { kUpdate = 0, kChase = 1, kAed = 2, kSmall = 3, kOther = 4, kRecDefl = 5 };
+    enum Kind { kUpdate = 0, kChase = 1, kAed = 2, kSmall = 3, kOther = 4, kRecDefl = 5, kUpdateFar = 6 };
     struct Mark {
         int kind;
         hipEvent_t a, b;
@@ -332,6 +332,10 @@ class Solver {
             ck(hipEventElapsedTime(&ms, m.a, m.b));
             switch (m.kind) {
                 case kUpdate: stats_.gpu_update_ms += ms; stats_.n_update += 1; break;
+                case kUpdateFar:
+                    stats_.gpu_update_ms += ms; stats_.n_update += 1;
+                    stats_.gpu_update_far_ms += ms; stats_.n_update_far += 1;
+                    break;
                 case kChase: stats_.gpu_chase_ms += ms; stats_.n_chase += 1; break;
                 case kAed: stats_.gpu_aed_ms += ms; break;
                 case kSmall: stats_.gpu_small_ms += ms; break;
@@ -391,12 +395,13 @@ class Solver {
         int ldc, ldu, w, len, side;
     };
 
-    void run_updates(const std::vector<Task> &all) { run_updates(all, st_); }
+    void run_updates(const std::vector<Task> &all) { run_updates(all, st_, kUpdate); }
 
-    void run_updates(const std::vector<Task> &all, hipStream_t s) {
+    // kind: kUpdate, or kUpdateFar for the far part of an overlapped sweep step
+    void run_updates(const std::vector<Task> &all, hipStream_t s, int kind) {
         std::vector<Task> tasks, wide;
         for (const Task &t : all) (t.w > UPD_WMAX ? wide : tasks).push_back(t);
-        run_updates_wide(wide, s);
+        run_updates_wide(wide, s, kind);
         size_t i = 0;
         while (i < tasks.size()) {
             UpdArgs a;
@@ -410,29 +415,34 @@ class Solver {
                 u.tile0 = tiles;
                 tiles += (t.len + UPD_SLICE - 1) / UPD_SLICE;
                 wmaxp = std::max(wmaxp, (t.w + 15) & ~15);
-                stats_.gemm_flops += 2.0 * t.w * (double)t.w * t.len;
+                count_update_flops(2.0 * t.w * (double)t.w * t.len, kind);
             }
             a.ntask = nt;
             if (nt == 0 || tiles == 0) continue;
-            launch_update_p(a, tiles, (wmaxp + 15) / 16, s);
+            launch_update_p(a, tiles, (wmaxp + 15) / 16, s, kind);
         }
     }
 
-    void launch_update_p(const UpdArgs &a, int nslice, int nrt, hipStream_t s) {
+    void count_update_flops(double f, int kind) {
+        stats_.gemm_flops += f;
+        if (kind == kUpdateFar) stats_.gemm_flops_far += f;
+    }
+
+    void launch_update_p(const UpdArgs &a, int nslice, int nrt, hipStream_t s, int kind) {
         switch (nrt) {
-            case 1: launch_update_nrt<1>(a, nslice, s); break;
-            case 2: launch_update_nrt<2>(a, nslice, s); break;
-            case 3: launch_update_nrt<3>(a, nslice, s); break;
-            case 4: launch_update_nrt<4>(a, nslice, s); break;
-            case 5: launch_update_nrt<5>(a, nslice, s); break;
-            default: launch_update_nrt<6>(a, nslice, s); break;
+            case 1: launch_update_nrt<1>(a, nslice, s, kind); break;
+            case 2: launch_update_nrt<2>(a, nslice, s, kind); break;
+            case 3: launch_update_nrt<3>(a, nslice, s, kind); break;
+            case 4: launch_update_nrt<4>(a, nslice, s, kind); break;
+            case 5: launch_update_nrt<5>(a, nslice, s, kind); break;
+            default: launch_update_nrt<6>(a, nslice, s, kind); break;
         }
     }
 
     template <int NRT>
-    void launch_update_nrt(const UpdArgs &a, int nslice, hipStream_t s) {
+    void launch_update_nrt(const UpdArgs &a, int nslice, hipStream_t s, int kind) {
         const int grid = std::min(nslice, ws_.cus * update_p_occupancy<NRT>(ws_));
-        timed_on(s, kUpdate, [&] {
+        timed_on(s, kind, [&] {
             hipLaunchKernelGGL(k_update_p<NRT>, dim3(grid), dim3(64 * NRT), update_p_lds(NRT), s, a, nslice);
             ck(hipGetLastError());
         });
@@ -440,7 +450,7 @@ class Solver {
 
     // tasks with factors of order UPD_WMAX+1 .. UPW_WMAX: U^T streamed from L2,
     // only the strip's slice staged in LDS
-    void run_updates_wide(const std::vector<Task> &tasks, hipStream_t s) {
+    void run_updates_wide(const std::vector<Task> &tasks, hipStream_t s, int kind) {
         size_t i = 0;
         while (i < tasks.size()) {
             UpdArgs a;
@@ -455,14 +465,14 @@ class Solver {
                 u.tile0 = tiles;
                 tiles += (t.len + UPW_SLICE - 1) / UPW_SLICE;
                 wmaxp = std::max(wmaxp, (t.w + 63) & ~63);
-                stats_.gemm_flops += 2.0 * t.w * (double)t.w * t.len;
+                count_update_flops(2.0 * t.w * (double)t.w * t.len, kind);
             }
             a.ntask = nt;
             if (nt == 0 || tiles == 0) continue;
             // side 0 stages wp x UPW_SLICE with leading dimension wp + 1, side 1
             // UPW_SLICE x wp with leading dimension UPW_SLICE + 1
             const size_t lds = (size_t)(wmaxp + 1) * (UPW_SLICE + 1) * sizeof(double);
-            timed_on(s, kUpdate, [&] {
+            timed_on(s, kind, [&] {
                 hipLaunchKernelGGL(k_update_wide, dim3(tiles), dim3(UPW_THREADS), lds, s, a);
                 ck(hipGetLastError());
             });
@@ -640,6 +650,9 @@ class Solver {
             stats_.aed_flops += q.aed_flops;  // the inner k_aed launches
             stats_.aed_launches += q.aed_launches;
             stats_.gpu_update_ms += q.gpu_update_ms;
+            stats_.gpu_update_far_ms += q.gpu_update_far_ms;
+            stats_.n_update_far += q.n_update_far;
+            stats_.gemm_flops_far += q.gemm_flops_far;
             stats_.gpu_chase_ms += q.gpu_chase_ms;
             stats_.gpu_aed_ms += q.gpu_aed_ms;
             stats_.gpu_small_ms += q.gpu_small_ms;
@@ -723,15 +736,15 @@ class Solver {
 
     // One launch when no left strip meets a right strip, else every left strip
     // first (each pair commutes, but not within one launch).
-    void run_parts(Parts &p, hipStream_t s) {
+    void run_parts(Parts &p, hipStream_t s, int kind) {
         if (!p.cross()) {
             p.l.insert(p.l.end(), p.r.begin(), p.r.end());
             p.l.insert(p.l.end(), p.z.begin(), p.z.end());
-            run_updates(p.l, s);
+            run_updates(p.l, s, kind);
         } else {
-            run_updates(p.l, s);
+            run_updates(p.l, s, kind);
             p.r.insert(p.r.end(), p.z.begin(), p.z.end());
-            run_updates(p.r, s);
+            run_updates(p.r, s, kind);
         }
     }
 
@@ -859,13 +872,13 @@ class Solver {
             }
             if (ovl) {
                 if (step > 0) ck(hipStreamWaitEvent(st_, ws_.ev_far, 0));
-                run_parts(near, st_);
+                run_parts(near, st_, kUpdate);
                 ck(hipEventRecord(ws_.ev_near, st_));
                 ck(hipStreamWaitEvent(ws_.ust, ws_.ev_near, 0));
-                run_parts(far, ws_.ust);
+                run_parts(far, ws_.ust, kUpdateFar);
                 ck(hipEventRecord(ws_.ev_far, ws_.ust));
             } else {
-                run_parts(far, st_);  // lo > hi: everything is in the far part
+                run_parts(far, st_, kUpdate);  // lo > hi: everything is in the far part
             }
         }
         if (ovl && step > 0) ck(hipStreamWaitEvent(st_, ws_.ev_far, 0));

@@ -126,3 +126,36 @@ def test_product_path_has_no_cpu_fallback():
     H = torch.zeros((4, 4), dtype=torch.float64).t()
     with pytest.raises(binding.NeigError):
         binding.schur(H)
+
+
+def header_struct_fields(name):
+    """(field, C type) in declaration order of `typedef struct name {...} name;`
+    in the header (comments removed; one type per declaration, several names)."""
+    text = re.sub(r"/\*.*?\*/", "", open(HEADER).read(), flags=re.S)
+    body = re.search(r"typedef struct %s \{(.*?)\} %s;" % (name, name), text, flags=re.S).group(1)
+    fields = []
+    for decl in body.split(";"):
+        decl = " ".join(decl.split())
+        if not decl:
+            continue
+        m = re.match(r"(long long|double|int)\s+(.*)", decl)
+        assert m, decl
+        for f in m.group(2).split(","):
+            f = f.strip()
+            arr = re.match(r"(\w+)\[(\d+)\]", f)
+            fields.append((arr.group(1), m.group(1), int(arr.group(2))) if arr else (f, m.group(1), 1))
+    return fields
+
+
+@pytest.mark.parametrize("cname,pyname", [("neig_params", "Params"), ("neig_stats", "Stats")])
+def test_binding_structs_match_the_header(cname, pyname):
+    """The binding's ctypes mirrors of the parameter and statistics structs have
+    the header's fields, in its order, with its types."""
+    from paper_2002_05024_amd import binding
+
+    ctype = {"int": ctypes.c_int, "double": ctypes.c_double, "long long": ctypes.c_longlong}
+    want = header_struct_fields(cname)
+    got = getattr(binding, pyname)._fields_
+    assert [f for f, _ in got] == [f for f, _, _ in want]
+    for (f, t), (_, ct, cnt) in zip(got, want):
+        assert t == (ctype[ct] * cnt if cnt > 1 else ctype[ct]), f
