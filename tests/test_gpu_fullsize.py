@@ -122,6 +122,46 @@ def test_random_hessenberg_n20000(neig):
     assert abs((lam * lam).sum() - tr2) <= 50 * n * n * EPS * nh * nh
 
 
+def test_dense_uniform_n10000_overlapped_sweeps(neig):
+    """The sweep-heavy input above the order from which the sweeps' far updates
+    run on the second stream (Hessenberg form, by neig_hessenberg, of a dense
+    uniform[-1, 1] matrix; 64 shifts in chains of 8, 64-row chase windows):
+    backward error and orthogonality with GPU products, exact structure, the
+    trace invariants, and the far parts counted."""
+    import torch
+
+    import bench
+    from paper_2002_05024_amd import binding
+
+    n = 10000
+    say(f"dense uniform n={n}, overlapped sweeps")
+    g = inputs.rng(inputs.FULL, 47)
+    A = torch.from_numpy(g.uniform(-1.0, 1.0, (n, n))).to("cuda:0").t()
+    binding.hessenberg(A)
+    A.triu_(-1)
+    H = A.clone(memory_format=torch.preserve_format)
+    neig.set_params(ns=64, nw=80, chain=8, chase_w=64, overlap=0)
+    try:
+        r = neig.schur(H)
+        st = neig.get_stats()
+    finally:
+        neig.set_params(ns=0, nw=0, chain=0, chase_w=0)
+    say(f"  sweeps {st['sweeps']} aeds {st['aeds']} far flops {st['gemm_flops_far']:.3e}")
+    assert r.info == 0
+    assert st["sweeps"] > 0 and st["gemm_flops_far"] > 0
+    be, oe = bench.backward_and_orth(A, H, r.Z)
+    say(f"  backward {be:.2e} orth {oe:.2e}")
+    assert be <= 50 * n * EPS and oe <= 50 * n * EPS
+    assert structure_on_gpu(H) == 0
+    wr, wi = r.wr.cpu().numpy(), r.wi.cpu().numpy()
+    h0d = torch.diagonal(A).cpu().numpy()
+    tr2 = np.sum(h0d ** 2) + 2 * np.sum(torch.diagonal(A, 1).cpu().numpy() * torch.diagonal(A, -1).cpu().numpy())
+    nh = float(torch.linalg.norm(A))
+    lam = wr + 1j * wi
+    assert abs(lam.sum() - h0d.sum()) <= 50 * np.sqrt(n) * n * EPS * nh
+    assert abs((lam * lam).sum() - tr2) <= 50 * n * n * EPS * nh * nh
+
+
 def test_plain_n256_all_seeds(neig):
     """The plain workload, all 32 seeds: full oracle parity at n = 256."""
     from checks import backward_error, orthogonality
