@@ -365,7 +365,7 @@ def hard_leg(args, dev):
     table = autotune_single.load()
     hp = None
     if table and "hard_optimum" in table:
-        hp = {k: table["hard_optimum"][k] for k in ("ns", "nw", "chain", "chase_w")}
+        hp = {k: table["hard_optimum"][k] for k in autotune_single.KEYS if k in table["hard_optimum"]}
         binding.set_params(**hp)
     H = A.clone(memory_format=torch.preserve_format)
     Z = torch.zeros_like(A)

@@ -2,7 +2,9 @@
 
 The method's tunables (Section 3.2): the shifts per sweep ``ns``, the AED
 window ``nw`` (windows above 96 rows are solved recursively), the bulges per
-chain ``chain`` and the chase window ``chase_w``.  For each size bucket the
+chain ``chain``, the chase window ``chase_w`` and ``nibble``, the share of its
+window (percent) an AED must deflate to be followed by another AED instead of a
+sweep (how many AED steps run between sweeps, Section 5).  For each size bucket the
 tuner times ``neig_schur`` on that bucket's workload for candidate settings, by
 coordinate descent from the library's defaults, and keeps a candidate only if
 the solve converges and meets the backward-error and orthogonality bound
@@ -18,7 +20,9 @@ recorded beside the table, not used by it.  The table is saved as JSON next to
 this file; :func:`apply` sets the parameters of the bucket an order falls in
 through ``neig_set_params``.
 
-Usage (on a GPU): ``python -m paper_2002_05024_amd.autotune_single``.
+Usage (on a GPU): ``python -m paper_2002_05024_amd.autotune_single``;
+``--refine nibble`` re-tunes only the named parameters of a saved table, from
+its entries.
 """
 from __future__ import annotations
 
@@ -37,8 +41,10 @@ GRID = {
     "nw": [48, 64, 80, 96, 128, 192],
     "chain": [8, 12, 16],
     "chase_w": [64, 80, 96],
+    "nibble": [4, 8, 14, 25],
 }
-DEFAULT = {"ns": 32, "nw": 64, "chain": 16, "chase_w": 96}
+DEFAULT = {"ns": 32, "nw": 64, "chain": 16, "chase_w": 96, "nibble": 14}
+KEYS = tuple(DEFAULT)
 
 
 def _valid(p) -> bool:
@@ -87,7 +93,8 @@ class Timer:
 
         from . import binding
 
-        binding.set_params(ns=p["ns"], nw=p["nw"], chain=p["chain"], chase_w=p["chase_w"])
+        binding.set_params(ns=p["ns"], nw=p["nw"], chain=p["chain"], chase_w=p["chase_w"],
+                           nibble=p.get("nibble", 0))
         self.H.copy_(self.H0)
         self.Z.zero_()
         self.Z.diagonal().fill_(1.0)
@@ -115,17 +122,21 @@ class Timer:
         return sec
 
 
-def tune_workload(timer, passes: int = 2, log=print):
-    """Coordinate descent over GRID from DEFAULT; returns (best params, seconds,
-    default seconds, trials)."""
+def tune_workload(timer, passes: int = 2, log=print, start=None, keys=None):
+    """Coordinate descent over GRID (the given keys only, if any) from DEFAULT
+    or from ``start``; returns (best params, seconds, starting seconds, trials)."""
     best = dict(DEFAULT)
+    if start:
+        best.update(start)
     t_def = timer.run(best)
     best_t = t_def
     trials = [(dict(best), t_def)]
-    log(f"  default {best} {t_def}")
+    log(f"  start {best} {t_def}")
     for _ in range(passes):
         improved = False
         for key, vals in GRID.items():
+            if keys and key not in keys:
+                continue
             for v in vals:
                 if v == best[key]:
                     continue
@@ -185,8 +196,38 @@ def load(path: str = SAVED):
 def params_for(n: int, table) -> dict:
     for b in table["buckets"]:
         if b["n_hi"] is None or n <= b["n_hi"]:
-            return {k: b[k] for k in ("ns", "nw", "chain", "chase_w")}
+            return {k: b[k] for k in KEYS if k in b}
     return dict(DEFAULT)
+
+
+def refine(keys, path: str = SAVED, passes: int = 1, log=print):
+    """Re-tune only ``keys`` of a saved table: coordinate descent from each
+    bucket's entry (and from the recorded optimum for the dense-uniform input)
+    on that entry's own workload."""
+    import torch
+
+    from . import binding
+
+    table = load(path)
+    dev = torch.device("cuda:0")
+    binding.load_library()
+    saved = binding.get_params()
+    try:
+        entries = list(table["buckets"]) + ([table["hard_optimum"]] if "hard_optimum" in table else [])
+        for e in entries:
+            kind, n = e["workload"].split(" n=")
+            log(f"refine {keys} on {kind} n={n}")
+            timer = Timer(workload(kind, int(n), dev))
+            start = {k: e[k] for k in KEYS if k in e}
+            best, t, t0, trials = tune_workload(timer, passes, log, start=start, keys=keys)
+            e.update(best)
+            e["seconds"] = t
+            e.setdefault("refined", []).append({"keys": list(keys), "trials": len(trials), "start_seconds": t0})
+            del timer
+            torch.cuda.empty_cache()
+    finally:
+        binding.set_params(**saved)
+    return table
 
 
 def apply(n: int, path: str = SAVED):
@@ -209,8 +250,13 @@ def main():
     ap.add_argument("--large", type=int, default=20000)
     ap.add_argument("--hard", type=int, default=0)
     ap.add_argument("--passes", type=int, default=2)
+    ap.add_argument("--refine", nargs="*", default=None, help="re-tune only these parameters of the saved table")
     a = ap.parse_args()
-    table = tune(a.small, a.large, a.hard, a.passes, log=lambda *x: print(*x, file=sys.stderr, flush=True))
+    log = lambda *x: print(*x, file=sys.stderr, flush=True)  # noqa: E731
+    if a.refine:
+        table = refine(tuple(a.refine), a.out, 1, log)
+    else:
+        table = tune(a.small, a.large, a.hard, a.passes, log=log)
     with open(a.out, "w") as f:
         json.dump(table, f, indent=1)
     print(json.dumps(table), flush=True)
