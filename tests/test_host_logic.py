@@ -173,3 +173,20 @@ def test_compact_runs_keeps_first_decisions(tmp_path):
     r1 = learn.per_matrix_rows(full["run"], full["arm"], full["t_def"], full["t_run"], full["feat"])
     r2 = learn.per_matrix_rows(c["run"], c["arm"], c["t_def"], c["t_run"], c["feat"])
     assert all(np.array_equal(x, y) for x, y in zip(r1, r2))
+
+
+def test_single_tuner_table_buckets_and_keys():
+    """The committed single-matrix table: each order falls in one bucket, whose
+    entries are valid library parameters (nibble included), and older tables
+    without nibble still give their four keys."""
+    from paper_2002_05024_amd import autotune_single as at
+
+    table = at.load()
+    assert table is not None
+    small, large = at.params_for(4000, table), at.params_for(20000, table)
+    assert set(small) == set(large) == set(at.KEYS)
+    for p in (small, large, {k: table["hard_optimum"][k] for k in at.KEYS}):
+        assert at._valid(p) and p["nibble"] in at.GRID["nibble"]
+    assert at.params_for(6000, table) == small and at.params_for(6001, table) == large
+    old = {"buckets": [{"n_hi": None, "ns": 32, "nw": 64, "chain": 8, "chase_w": 96}]}
+    assert at.params_for(100, old) == {"ns": 32, "nw": 64, "chain": 8, "chase_w": 96}
